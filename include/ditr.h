@@ -1,0 +1,148 @@
+/*
+ * ditr.h — D-iteration fluid diffusion on AMD Instinct MI355X (gfx950).
+ *
+ * Solves X = P X + B for the PageRank-type matrix P with p_ji = d / #out_i on
+ * every out-link i -> j (a dangling node has an all-zero column), by the
+ * D-iteration of Hong, arXiv:1202.6168: a fluid vector F (F_0 = B) and a
+ * history vector H (H_0 = 0) evolve by node diffusions
+ *     sent = F_i;  H_i += sent;  F_i = 0;  F_j += sent * p_ji for each child j
+ * (Section 2, equations defF and defH, and the Section 2.1 pseudo-code) until
+ * ||F||_1 falls below a target. H then approximates X with
+ * ||X - H||_1 <= ||F||_1 / (1 - d) (Section 2, the bound after defH).
+ *
+ * Conventions shared by every entry point:
+ *   - Graphs are CSC with int32 indices: column i, entries
+ *     col_ptr[i] .. col_ptr[i+1]-1 of row_idx, lists the out-neighbours of
+ *     node i. Self-loops and repeated entries are legal; each entry carries
+ *     d / #out_i. n < 2^31, nnz < 2^31.
+ *   - "d_" pointers are DEVICE pointers on the context's device; the caller
+ *     allocates and owns them (PyTorch tensors in the Python binding). The
+ *     library keeps non-owning references: a graph borrows its CSC arrays,
+ *     which must outlive the graph. "h_" pointers are host memory.
+ *   - Every call is asynchronous on the context's stream unless it says it
+ *     synchronizes. Calls that return host values synchronize the stream.
+ *   - Every function returns a ditr_status. No exception or abort crosses
+ *     the ABI; ditr_last_error() gives a message for the calling thread.
+ *   - A context is used from one host thread at a time (ditr_abort excepted).
+ */
+#ifndef DITR_H
+#define DITR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DITR_ABI_VERSION 1
+
+typedef enum {
+  DITR_OK = 0,
+  DITR_NOT_CONVERGED = 1, /* budget hit; H and F are valid (F = B + P H - H holds) */
+  DITR_ABORTED = 2,       /* ditr_abort() was called; H and F are valid */
+  DITR_EINVAL = -1,       /* bad argument (null pointer, size, damping outside (0,1), ...) */
+  DITR_EGRAPH = -2,       /* CSC is malformed (col_ptr not monotone, row out of range, ...) */
+  DITR_ENOMEM = -3,       /* device or pinned host allocation failed */
+  DITR_EHIP = -4,         /* a HIP runtime call failed */
+  DITR_ENONFINITE = -5    /* B or H_0 holds NaN or Inf */
+} ditr_status;
+
+typedef struct ditr_ctx ditr_ctx;     /* one device + one stream; opaque */
+typedef struct ditr_graph ditr_graph; /* uploaded CSC + partition plan + transpose; opaque */
+
+/* Node-set partition types of Section 2.3. */
+enum { DITR_PART_CB = 0,       /* cost-balanced: contiguous ranges of ~L/K out-links */
+       DITR_PART_UNIFORM = 1   /* contiguous ranges of floor(N/K) ids, last one takes the rest */ };
+
+/* Diffusion kernels. */
+enum { DITR_MODE_AUTO = 0,       /* persistent when the plan allows it */
+       DITR_MODE_PERSISTENT = 1, /* workgroups own partitions held in LDS (Sections 2.3-2.6) */
+       DITR_MODE_SWEEP = 2       /* one grid-wide threshold sweep per launch, fluid in HBM */ };
+
+typedef struct {
+  double alpha;        /* threshold divisor after each sweep (Section 2.4); > 1; default 1.5 */
+  double refresh_at;   /* first exact FP64 residual refresh once ||F||_1 <= refresh_at ||B||_1
+                          (cancels FP32 rounding drift); default 1e-5 */
+  double park_ratio;   /* a partition idles while its fluid is below park_ratio times its
+                          node share of the remaining fluid (Section 2.4, r_k < T); default 0.5 */
+  double rescale_cap;  /* max factor a reception may raise a partition threshold (Section 2.6) */
+  int32_t mode;        /* DITR_MODE_* */
+  int32_t part_type;   /* DITR_PART_* */
+  int32_t part_nodes;  /* nodes per partition target; 0 = from LDS capacity */
+  int32_t block;       /* threads per workgroup (64..1024, multiple of 64); 0 = auto */
+  int32_t wg_per_cu;   /* resident workgroups per CU for the persistent kernel; 0 = auto */
+  int32_t sweeps_per_claim; /* local sweeps per partition claim when partitions outnumber
+                               workgroups; 0 = auto */
+  int32_t max_rounds;  /* persistent launches (each followed by an exact residual) */
+  int32_t max_sweeps;  /* sweep budget per launch and workgroup (0 = auto) */
+  int32_t xcd_remap;   /* 1: place neighbouring partitions on the same XCD */
+  uint32_t flags;      /* reserved, 0 */
+} ditr_opts;
+
+typedef struct {
+  int64_t edges;       /* elementary edge diffusions (Section 2.4: normalized iterations x L) */
+  int64_t diffusions;  /* node diffusions */
+  int64_t sweeps;      /* partition sweeps summed over workgroups (persistent) or grid sweeps */
+  int64_t launches;    /* diffusion kernel launches */
+  int64_t refreshes;   /* exact FP64 residual refreshes F = B + P H - H */
+  int64_t idle_polls;  /* polls of an idle workgroup on its inbox (Section 3.3 idle time) */
+  double resid_l1;     /* final exact ||F||_1 (FP64, from the last refresh) */
+  double b_l1;         /* ||B||_1 */
+  double seconds;      /* host wall time of the call */
+  int32_t rounds;      /* outer rounds used */
+  int32_t status;      /* same as the return value */
+} ditr_stats;
+
+/* ---- library and context ---------------------------------------------- */
+int ditr_version(void);
+const char* ditr_last_error(void); /* thread-local; valid until the thread's next call */
+int ditr_opts_default(ditr_opts* o);
+
+/* Create a context on `device` that issues work on `hip_stream` (a hipStream_t;
+ * NULL = the null stream). Allocates a pinned host abort word. */
+int ditr_create(ditr_ctx** out, int device, void* hip_stream);
+int ditr_destroy(ditr_ctx* ctx);
+/* Ask a running ditr_solve on this context to stop (thread-safe). The solver
+ * returns DITR_ABORTED with a consistent (H, F). Cleared by the next solve. */
+int ditr_abort(ditr_ctx* ctx);
+
+/* ---- graph (step: upload and partition plan) --------------------------- */
+/* Validate the CSC on the device, build the transpose (CSR, used by the exact
+ * residual) and the partition plan of Section 2.3 (type and size from opts;
+ * NULL = defaults). Synchronizes. Errors: DITR_EGRAPH for a malformed CSC,
+ * DITR_EINVAL for bad sizes or damping outside (0, 1). */
+int ditr_graph_create(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64_t nnz,
+                      const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
+                      const ditr_opts* opts);
+int ditr_graph_destroy(ditr_graph* g);
+/* Number of partitions K of the plan and, if h_ptr != NULL and cap >= K+1,
+ * the boundaries omega_0 = 0 < ... <= omega_K = n. Synchronizes. */
+int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, int64_t cap);
+/* Standalone partition plan kernel (Section 2.3): writes K+1 boundaries to
+ * d_ptr (device int64). CB: omega_k = min { j : K * col_ptr[j] >= k * nnz }. */
+int ditr_partition(ditr_ctx* ctx, int64_t n, const int32_t* d_col_ptr, int part_type, int64_t K,
+                   int64_t* d_ptr);
+
+/* ---- plain solve (steps: init, diffusion, transfer, residual, refresh) -- */
+/* Exact residual F = B + P H - H (identity of equations defF and defH):
+ * FP64 arithmetic, FP32 store into d_f [n]. If h_resid != NULL the FP64
+ * ||F||_1 before rounding is returned there (synchronizes). */
+int ditr_residual(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, const double* d_h,
+                  float* d_f, double* h_resid);
+
+/* Diffuse until ||F||_1 <= rel_tol * ||B||_1 (checked on the exact FP64
+ * residual). d_b FP64 [n] (finite), d_h FP64 [n], d_f FP32 [n].
+ *   warm = 0: start from H = 0, F = B (d_h is overwritten).
+ *   warm = 1: start from the H_0 held in d_h; F_0 = B + P H_0 - H_0
+ *             (warm start and resume).
+ * On return d_h = H and d_f = the exact residual of H rounded to FP32.
+ * Synchronizes. Returns DITR_OK, DITR_NOT_CONVERGED, DITR_ABORTED or an error;
+ * `stats` (may be NULL) is filled in every case. */
+int ditr_solve(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
+               int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DITR_H */

@@ -1,0 +1,183 @@
+/*
+ * dref — plain sequential FP64 D-iteration: the ORACLE.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing but the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load or call this library; the GPU
+ * library never does, and the two share no code.
+ *
+ * What it computes (Hong, "D-iteration: evaluation of the asynchronous
+ * distributed computation", arXiv:1202.6168):
+ *   - the fluid recursion F_n = (I - J_{i_n} + P J_{i_n}) F_{n-1}, F_0 = B
+ *     (Section 2, equation defF) and the history H_n = sum_k J_{i_k} F_{k-1}
+ *     (equation defH), run in the order of the Section 2.1 pseudo-code:
+ *     take the fluid of node i, add it to H_i, zero F_i, give sent * p_ji to
+ *     every child j;
+ *   - node choice by the cyclic threshold test of Section 2.4: scan ids in
+ *     ascending order, diffuse every node with |F_i| > T, then T <- T / alpha;
+ *   - PageRank matrix of Section 2.2: p_ji = d / #out_i for each out-link
+ *     i -> j; a node without out-link (dangling) only moves F_i into H_i;
+ *   - partitions of Section 2.3: uniform and cost-balanced (CB).
+ *
+ * Readings of points the paper leaves open (all listed in the design notes):
+ *   - stop when ||F||_1 <= rel_tol * ||B||_1 (the paper's r/(1-d) test with
+ *     a relative target); r is recomputed once per sweep (Remark after the
+ *     pseudo-code), as an FP64 sum in index order;
+ *   - T_0 = max_i |F_i| / alpha; strict test |F_i| > T; if a sweep diffuses
+ *     nothing, T <- min(T, max|F| / alpha) so the run never stalls;
+ *   - a warm start H_0 gives F_0 = B + P H_0 - H_0, which follows from the two
+ *     recursions (F_n - F_{n-1} = (P - I)(H_n - H_{n-1})).
+ */
+#define _POSIX_C_SOURCE 199309L
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+typedef struct {
+  int64_t edges;       /* elementary diffusions (one per out-link of a diffused node) */
+  int64_t diffusions;  /* node diffusions */
+  int64_t sweeps;      /* cyclic passes over all ids */
+  int64_t increases;   /* sweeps after which ||F||_1 grew (expected 0) */
+  double resid_l1;     /* final ||F||_1 */
+  double b_l1;         /* ||B||_1 */
+  double seconds;      /* wall time of the iteration (steady clock) */
+  int32_t converged;   /* 1 if resid_l1 <= rel_tol * b_l1 */
+  int32_t pad;
+} dref_stats;
+
+enum { DREF_OK = 0, DREF_NOT_CONVERGED = 1, DREF_EINVAL = -1, DREF_EGRAPH = -2, DREF_ENOMEM = -3 };
+
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return ts.tv_sec + 1e-9 * ts.tv_nsec;
+}
+
+/* CSC sanity: col_ptr[0] = 0, non-decreasing, col_ptr[n] = nnz, rows in [0, n). */
+int dref_check_csc(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx) {
+  if (n < 0 || nnz < 0) return DREF_EINVAL;
+  if (col_ptr[0] != 0 || col_ptr[n] != nnz) return DREF_EGRAPH;
+  for (int64_t i = 0; i < n; ++i)
+    if (col_ptr[i + 1] < col_ptr[i]) return DREF_EGRAPH;
+  for (int64_t e = 0; e < nnz; ++e)
+    if (row_idx[e] < 0 || row_idx[e] >= n) return DREF_EGRAPH;
+  return DREF_OK;
+}
+
+/* F = B + P H - H, straight from the definition of P (column i spreads
+ * d / #out_i on each of its entries). */
+int dref_fluid_from_history(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                            double d, const double* b, const double* h, double* f) {
+  (void)nnz;
+  for (int64_t i = 0; i < n; ++i) f[i] = b[i] - h[i];
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t k = col_ptr[i + 1] - col_ptr[i];
+    if (k == 0) continue;
+    double p = d / (double)k;
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += p * h[i];
+  }
+  return DREF_OK;
+}
+
+static double norm1(const double* x, int64_t n) {
+  double s = 0;
+  for (int64_t i = 0; i < n; ++i) s += fabs(x[i]);
+  return s;
+}
+static double norminf(const double* x, int64_t n) {
+  double m = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (fabs(x[i]) > m) m = fabs(x[i]);
+  return m;
+}
+
+/*
+ * Sequential D-iteration until ||F||_1 <= rel_tol * ||B||_1.
+ *   h0       optional warm start (NULL = zero history)
+ *   h, f     outputs [n]: history and remaining fluid
+ *   r_hist   optional [r_hist_cap] record of ||F||_1 after each sweep
+ * Returns DREF_OK, DREF_NOT_CONVERGED (max_sweeps hit; h, f still valid) or
+ * a negative error.
+ */
+int dref_solve(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx, double d,
+               const double* b, const double* h0, double rel_tol, double alpha, int64_t max_sweeps,
+               double* h, double* f, dref_stats* st, double* r_hist, int64_t r_hist_cap) {
+  memset(st, 0, sizeof(*st));
+  if (!(d > 0 && d < 1) || !(alpha > 1) || !(rel_tol >= 0)) return DREF_EINVAL;
+  int rc = dref_check_csc(n, nnz, col_ptr, row_idx);
+  if (rc) return rc;
+
+  double t_start = now_s();
+  if (h0) {
+    memcpy(h, h0, sizeof(double) * n);
+    dref_fluid_from_history(n, nnz, col_ptr, row_idx, d, b, h, f);
+  } else {
+    memset(h, 0, sizeof(double) * n);
+    memcpy(f, b, sizeof(double) * n);
+  }
+  st->b_l1 = norm1(b, n);
+  const double target = rel_tol * st->b_l1;
+  double r = norm1(f, n);
+  double T = norminf(f, n) / alpha;
+
+  while (r > target && st->sweeps < max_sweeps) {
+    int64_t passed = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(fabs(f[i]) > T)) continue;
+      double sent = f[i];
+      h[i] += sent;
+      f[i] = 0.0;
+      int64_t k = col_ptr[i + 1] - col_ptr[i];
+      if (k > 0) {
+        double p = d / (double)k; /* p_ji for every child j of i */
+        for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += sent * p;
+      }
+      st->edges += k;
+      st->diffusions += 1;
+      ++passed;
+    }
+    st->sweeps += 1;
+    double r_new = norm1(f, n);
+    if (r_new > r) st->increases += 1;
+    r = r_new;
+    if (r_hist && st->sweeps <= r_hist_cap) r_hist[st->sweeps - 1] = r;
+    T /= alpha;
+    if (passed == 0) {
+      double m = norminf(f, n) / alpha;
+      if (m < T) T = m;
+    }
+  }
+  st->resid_l1 = r;
+  st->converged = r <= target;
+  st->seconds = now_s() - t_start;
+  return st->converged ? DREF_OK : DREF_NOT_CONVERGED;
+}
+
+/* Uniform partition (Section 2.3): K contiguous ranges of floor(n/K) ids, the
+ * last one also taking the remainder. ptr has K+1 entries. */
+int dref_partition_uniform(int64_t n, int64_t K, int64_t* ptr) {
+  if (K < 1 || K > (n > 0 ? n : 1)) return DREF_EINVAL;
+  int64_t q = n / K;
+  for (int64_t k = 0; k < K; ++k) ptr[k] = k * q;
+  ptr[K] = n;
+  return DREF_OK;
+}
+
+/* Cost-balanced partition (Section 2.3): contiguous ranges whose out-link
+ * counts equal L/K as nearly as integers allow. omega_k is the first id whose
+ * out-link prefix reaches k L / K, i.e. the smallest j with
+ * K * col_ptr[j] >= k * L (exact integer comparison, so the K = 2 split
+ * reappears among the K = 4 boundaries). */
+int dref_partition_cb(int64_t n, const int32_t* col_ptr, int64_t K, int64_t* ptr) {
+  if (K < 1 || K > (n > 0 ? n : 1)) return DREF_EINVAL;
+  int64_t L = col_ptr[n];
+  int64_t j = 0;
+  ptr[0] = 0;
+  for (int64_t k = 1; k < K; ++k) {
+    while (j < n && (int64_t)col_ptr[j] * K < k * L) ++j;
+    ptr[k] = j;
+  }
+  ptr[K] = n;
+  return DREF_OK;
+}
