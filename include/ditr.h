@@ -51,14 +51,23 @@ typedef enum {
 typedef struct ditr_ctx ditr_ctx;     /* one device + one stream; opaque */
 typedef struct ditr_graph ditr_graph; /* uploaded CSC + partition plan + transpose; opaque */
 
-/* Node-set partition types of Section 2.3. */
+/* Node-set partition types (Section 2.3). */
 enum { DITR_PART_CB = 0,       /* cost-balanced: contiguous ranges of ~L/K out-links */
-       DITR_PART_UNIFORM = 1   /* contiguous ranges of floor(N/K) ids, last one takes the rest */ };
+       DITR_PART_UNIFORM = 1,  /* contiguous ranges of floor(N/K) ids, last one takes the rest */
+       DITR_PART_CB_INOUT = 2  /* contiguous ranges of ~2L/K in+out links: a partition's whole
+                                  link cost, in the spirit of the alternative balance the
+                                  paper proposes after the CB rule */ };
 
 /* Diffusion kernels. */
-enum { DITR_MODE_AUTO = 0,       /* persistent when the plan allows it */
-       DITR_MODE_PERSISTENT = 1, /* workgroups own partitions held in LDS (Sections 2.3-2.6) */
-       DITR_MODE_SWEEP = 2       /* one grid-wide threshold sweep per launch, fluid in HBM */ };
+enum { DITR_MODE_AUTO = 0,       /* = DITR_MODE_PARTITION */
+       DITR_MODE_ASYNC = 1,      /* persistent workgroups own partitions held in LDS and exchange
+                                    fluid through atomic inboxes, no grid-wide barrier
+                                    (Sections 2.3-2.6, asynchronous) */
+       DITR_MODE_SWEEP = 2,      /* one grid-wide threshold sweep per launch, pulled over the
+                                    transpose (Section 2.4 applied to a node set) */
+       DITR_MODE_PARTITION = 3   /* one launch = m local threshold sweeps per partition in LDS,
+                                    outside fluid pulled as p_ji times the H increment
+                                    (Sections 2.3-2.5, synchronous exchange) */ };
 
 typedef struct {
   double alpha;        /* threshold divisor after each sweep (Section 2.4); > 1; default 1.5 */
@@ -72,8 +81,9 @@ typedef struct {
   int32_t part_nodes;  /* nodes per partition target; 0 = from LDS capacity */
   int32_t block;       /* threads per workgroup (64..1024, multiple of 64); 0 = auto */
   int32_t wg_per_cu;   /* resident workgroups per CU for the persistent kernel; 0 = auto */
-  int32_t sweeps_per_claim; /* local sweeps per partition claim when partitions outnumber
-                               workgroups; 0 = auto */
+  int32_t sweeps_per_claim; /* ASYNC: local sweeps per partition claim when partitions
+                               outnumber workgroups; PARTITION: local sweeps per launch (m);
+                               0 = auto */
   int32_t max_rounds;  /* persistent launches (each followed by an exact residual) */
   int32_t max_sweeps;  /* sweep budget per launch and workgroup (0 = auto) */
   int32_t xcd_remap;   /* 1: place neighbouring partitions on the same XCD */
@@ -120,9 +130,12 @@ int ditr_graph_destroy(ditr_graph* g);
  * the boundaries omega_0 = 0 < ... <= omega_K = n. Synchronizes. */
 int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, int64_t cap);
 /* Standalone partition plan kernel (Section 2.3): writes K+1 boundaries to
- * d_ptr (device int64). CB: omega_k = min { j : K * col_ptr[j] >= k * nnz }. */
-int ditr_partition(ditr_ctx* ctx, int64_t n, const int32_t* d_col_ptr, int part_type, int64_t K,
-                   int64_t* d_ptr);
+ * d_ptr (device int64, 1 <= K <= n). CB: omega_k = min { j : K col_ptr[j] >= k nnz }.
+ * CB_INOUT: the same with col_ptr[j] + in_prefix[j] against 2 nnz, where
+ * in_prefix counts the entries of d_row_idx below j (d_row_idx may be NULL for
+ * the other types). Synchronizes for CB_INOUT (temporary in-link prefix). */
+int ditr_partition(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+                   const int32_t* d_row_idx, int part_type, int64_t K, int64_t* d_ptr);
 
 /* ---- plain solve (steps: init, diffusion, transfer, residual, refresh) -- */
 /* Exact residual F = B + P H - H (identity of equations defF and defH):

@@ -181,3 +181,26 @@ int dref_partition_cb(int64_t n, const int32_t* col_ptr, int64_t K, int64_t* ptr
   ptr[K] = n;
   return DREF_OK;
 }
+
+/* Cost-balanced partition on in+out links: the CB rule above with the cost of
+ * a prefix [0, j) taken as its out-links plus its in-links (in-links counted
+ * here from the row indices). omega_k = min { j : K cost(j) >= k 2L }. */
+int dref_partition_cb_inout(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                            int64_t K, int64_t* ptr) {
+  if (K < 1 || K > (n > 0 ? n : 1)) return DREF_EINVAL;
+  int64_t* cost = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!cost) return DREF_ENOMEM;
+  for (int64_t e = 0; e < nnz; ++e) cost[row_idx[e] + 1] += 1;   /* in-links of each node */
+  for (int64_t j = 0; j < n; ++j) cost[j + 1] += cost[j];         /* in-link prefix */
+  for (int64_t j = 0; j <= n; ++j) cost[j] += col_ptr[j];          /* + out-link prefix */
+  const int64_t total = cost[n];
+  int64_t j = 0;
+  ptr[0] = 0;
+  for (int64_t k = 1; k < K; ++k) {
+    while (j < n && cost[j] * K < k * total) ++j;
+    ptr[k] = j;
+  }
+  ptr[K] = n;
+  free(cost);
+  return DREF_OK;
+}

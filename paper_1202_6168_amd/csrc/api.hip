@@ -1,0 +1,493 @@
+// C-ABI of the ditr library: context, graph upload and partition plan,
+// exact residual, and the host driver of the plain solve.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "common.h"
+
+int persistent_occupancy(ditr_ctx* c, int block, size_t lds, int* per_cu);
+
+namespace {
+thread_local char g_err[1024] = "";
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t lds_bytes_for(int nodes) {
+  return (((size_t)nodes * 4 + 15) & ~(size_t)15) + (size_t)nodes * 8;
+}
+
+int read_ctrl(ditr_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return DITR_OK;
+}
+
+// Largest dynamic LDS (bytes) a persistent workgroup of `block` threads may take.
+int max_dynamic_lds(ditr_ctx* c, int block, size_t* out) {
+  const int slot = block == 256 ? 0 : block == 512 ? 1 : block == 1024 ? 2 : -1;
+  if (slot < 0) return set_error(DITR_EINVAL, "block must be 256, 512 or 1024");
+  *out = c->lds_dyn[slot];
+  return DITR_OK;
+}
+
+}  // namespace
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+extern "C" {
+
+int ditr_version(void) { return DITR_ABI_VERSION; }
+
+const char* ditr_last_error(void) { return g_err; }
+
+int ditr_opts_default(ditr_opts* o) {
+  if (!o) return set_error(DITR_EINVAL, "opts is NULL");
+  memset(o, 0, sizeof(*o));
+  o->alpha = 1.5;
+  o->refresh_at = 1e-5;
+  o->park_ratio = 0.5;
+  o->rescale_cap = 4.0;
+  o->mode = DITR_MODE_AUTO;
+  o->part_type = DITR_PART_CB_INOUT;
+  o->part_nodes = 0;
+  o->block = 1024;
+  o->wg_per_cu = 1;
+  o->sweeps_per_claim = 0;
+  o->max_rounds = 16;
+  o->max_sweeps = 0;
+  o->xcd_remap = 1;
+  o->flags = 0;
+  return DITR_OK;
+}
+
+int ditr_create(ditr_ctx** out, int device, void* hip_stream) {
+  if (!out) return set_error(DITR_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_error(DITR_EINVAL, "no device %d", device);
+  HIP_TRY(hipSetDevice(device));
+  ditr_ctx* c = new (std::nothrow) ditr_ctx();
+  if (!c) return set_error(DITR_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete c;
+    return set_error(DITR_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  }
+  c->num_cus = prop.multiProcessorCount;
+  c->lds_per_block = prop.sharedMemPerBlock;
+  c->lds_per_cu = std::max<size_t>(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
+  persistent_configure(c, c->lds_per_cu, c->lds_per_block);
+  part_configure(c);
+  c->partials_cap = 8192;
+  bool ok = hipHostMalloc((void**)&c->abort_host, sizeof(int), hipHostMallocMapped) == hipSuccess &&
+            hipHostGetDevicePointer((void**)&c->abort_dev, c->abort_host, 0) == hipSuccess &&
+            hipMalloc((void**)&c->ctrl, sizeof(Ctrl)) == hipSuccess &&
+            hipHostMalloc((void**)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess &&
+            hipMalloc((void**)&c->partials, sizeof(double) * 4 * c->partials_cap) == hipSuccess;
+  if (!ok) {
+    ditr_destroy(c);
+    return set_error(DITR_ENOMEM, "device or pinned allocation failed");
+  }
+  *c->abort_host = 0;
+  if (hipMemset(c->ctrl, 0, sizeof(Ctrl)) != hipSuccess) {
+    ditr_destroy(c);
+    return set_error(DITR_EHIP, "hipMemset failed");
+  }
+  *out = c;
+  return DITR_OK;
+}
+
+int ditr_destroy(ditr_ctx* c) {
+  if (!c) return DITR_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->abort_host) (void)hipHostFree(c->abort_host);
+  if (c->ctrl) (void)hipFree(c->ctrl);
+  if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
+  if (c->partials) (void)hipFree(c->partials);
+  delete c;
+  return DITR_OK;
+}
+
+int ditr_abort(ditr_ctx* c) {
+  if (!c || !c->abort_host) return set_error(DITR_EINVAL, "ctx is NULL");
+  __atomic_store_n(c->abort_host, 1, __ATOMIC_SEQ_CST);
+  return DITR_OK;
+}
+
+int ditr_partition(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+                   const int32_t* d_row_idx, int part_type, int64_t K, int64_t* d_ptr) {
+  if (!c || !d_col_ptr || !d_ptr) return set_error(DITR_EINVAL, "NULL argument");
+  if (n < 1 || K < 1 || K > n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
+  if (part_type != DITR_PART_CB && part_type != DITR_PART_UNIFORM && part_type != DITR_PART_CB_INOUT)
+    return set_error(DITR_EINVAL, "unknown partition type %d", part_type);
+  if (part_type == DITR_PART_CB_INOUT && nnz > 0 && !d_row_idx)
+    return set_error(DITR_EINVAL, "CB_INOUT needs the row indices");
+  HIP_TRY(hipSetDevice(c->device));
+  if (part_type != DITR_PART_CB_INOUT)
+    return launch_partition(c, n, d_col_ptr, nullptr, part_type, K, d_ptr, nullptr);
+  int32_t* in_prefix = nullptr;
+  HIP_TRY(hipMalloc((void**)&in_prefix, sizeof(int32_t) * (n + 1)));
+  int rc = launch_in_prefix(c, n, nnz, d_row_idx, in_prefix);
+  if (!rc) rc = launch_partition(c, n, d_col_ptr, in_prefix, part_type, K, d_ptr, nullptr);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(in_prefix);
+  return rc;
+}
+
+int ditr_graph_destroy(ditr_graph* g) {
+  if (!g) return DITR_OK;
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipStreamSynchronize(g->ctx->stream);
+  (void)hipFree(g->row_ptr);
+  (void)hipFree(g->csr_col);
+  (void)hipFree(g->heavy_rows);
+  (void)hipFree(g->chunk_h);
+  (void)hipFree(g->chunk_beg);
+  (void)hipFree(g->chunk_end);
+  (void)hipFree(g->pull_s);
+  (void)hipFree(g->pull_heavy);
+  (void)hipFree(g->pull_partials);
+  (void)hipFree(g->wh);
+  (void)hipFree(g->part_ptr);
+  (void)hipFree(g->part_T);
+  (void)hipFree(g->part_lock);
+  delete[] g->part_ptr_host;
+  free_part_plan(g);
+  delete g;
+  return DITR_OK;
+}
+
+// (re)build the partition plan with K parts; reads the boundaries back
+static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
+  (void)hipFree(g->part_ptr);
+  (void)hipFree(g->part_T);
+  (void)hipFree(g->part_lock);
+  g->part_ptr = nullptr;
+  g->part_T = nullptr;
+  g->part_lock = nullptr;
+  delete[] g->part_ptr_host;
+  g->part_ptr_host = new (std::nothrow) int64_t[K + 1];
+  if (!g->part_ptr_host) return set_error(DITR_ENOMEM, "host allocation failed");
+  g->K = K;
+  HIP_TRY(hipMalloc((void**)&g->part_ptr, sizeof(int32_t) * (K + 1)));
+  HIP_TRY(hipMalloc((void**)&g->part_T, sizeof(double) * K));
+  HIP_TRY(hipMalloc((void**)&g->part_lock, sizeof(int) * K));
+  HIP_TRY(hipMemsetAsync(g->part_lock, 0, sizeof(int) * K, c->stream));
+  int64_t* tmp = nullptr;
+  HIP_TRY(hipMalloc((void**)&tmp, sizeof(int64_t) * (K + 1)));
+  int rc = launch_partition(c, g->n, g->col_ptr, g->row_ptr, g->part_type, K, tmp, g->part_ptr);
+  hipError_t e = rc ? hipSuccess
+                    : hipMemcpyAsync(g->part_ptr_host, tmp, sizeof(int64_t) * (K + 1),
+                                     hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp);
+  if (rc) return rc;
+  HIP_TRY(e);
+  int64_t mx = 0;
+  for (int64_t k = 0; k < K; ++k) mx = std::max(mx, g->part_ptr_host[k + 1] - g->part_ptr_host[k]);
+  g->max_part = (int32_t)mx;
+  return DITR_OK;
+}
+
+int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
+                      const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
+                      const ditr_opts* opts) {
+  if (!c || !out) return set_error(DITR_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1 || n >= ((int64_t)1 << 31) - 1) return set_error(DITR_EINVAL, "n = %lld out of range", (long long)n);
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(DITR_EINVAL, "nnz = %lld out of range", (long long)nnz);
+  if (!(damping > 0 && damping < 1)) return set_error(DITR_EINVAL, "damping must lie in (0, 1)");
+  if (!d_col_ptr || (nnz > 0 && !d_row_idx)) return set_error(DITR_EINVAL, "NULL CSC array");
+  ditr_opts o;
+  ditr_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.part_type != DITR_PART_CB && o.part_type != DITR_PART_UNIFORM &&
+      o.part_type != DITR_PART_CB_INOUT)
+    return set_error(DITR_EINVAL, "unknown partition type %d", o.part_type);
+  if (o.block == 0) o.block = 1024;
+  if (o.block != 256 && o.block != 512 && o.block != 1024)
+    return set_error(DITR_EINVAL, "block must be 256, 512 or 1024");
+  HIP_TRY(hipSetDevice(c->device));
+
+  int rc = launch_validate_csc(c, n, nnz, d_col_ptr, d_row_idx);
+  if (rc) return rc;
+  rc = read_ctrl(c);
+  if (rc) return rc;
+  if (c->ctrl_host->err)
+    return set_error(DITR_EGRAPH, "malformed CSC (flags %d: 1 = col_ptr ends, 2 = decreasing "
+                     "col_ptr, 4 = row index out of range)", c->ctrl_host->err);
+
+  ditr_graph* g = new (std::nothrow) ditr_graph();
+  if (!g) return set_error(DITR_ENOMEM, "host allocation failed");
+  g->ctx = c;
+  g->n = n;
+  g->nnz = nnz;
+  g->d = damping;
+  g->col_ptr = d_col_ptr;
+  g->row_idx = d_row_idx;
+  g->part_type = o.part_type;
+  bool ok = hipMalloc((void**)&g->row_ptr, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            hipMalloc((void**)&g->csr_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) == hipSuccess &&
+            hipMalloc((void**)&g->heavy_rows, sizeof(int32_t) * n) == hipSuccess &&
+            hipMalloc((void**)&g->wh, sizeof(double) * n) == hipSuccess;
+  if (!ok) {
+    ditr_graph_destroy(g);
+    return set_error(DITR_ENOMEM, "device allocation failed (graph of n = %lld)", (long long)n);
+  }
+  rc = launch_build_transpose(c, g);
+  if (!rc) rc = build_heavy_chunks(c, g);
+  if (rc) {
+    ditr_graph_destroy(g);
+    return rc;
+  }
+
+  // partition plan (Section 2.3): sized so that one partition fits in LDS
+  size_t lds_max = 0;
+  rc = max_dynamic_lds(c, o.block, &lds_max);
+  if (rc) {
+    ditr_graph_destroy(g);
+    return rc;
+  }
+  // a partition's nodes must fit the LDS of both partitioned kernels
+  // (12 bytes per node for the asynchronous one, 20 for the partitioned sweep)
+  const int64_t cap_nodes = std::min<int64_t>(
+      65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 20)));
+  int64_t K;
+  if (o.part_nodes > 0) {
+    K = (n + o.part_nodes - 1) / o.part_nodes;
+  } else {
+    // about 4096 nodes per partition, and at least one partition per CU when n allows
+    K = std::max<int64_t>((n + 4095) / 4096, std::min<int64_t>(c->num_cus, n / 256));
+  }
+  K = std::max<int64_t>(1, std::min<int64_t>(K, n));
+  for (int attempt = 0;; ++attempt) {
+    rc = make_plan(c, g, K);
+    if (rc) {
+      ditr_graph_destroy(g);
+      return rc;
+    }
+    if (g->max_part <= cap_nodes) break;
+    if (attempt > 20 || K == n) {
+      ditr_graph_destroy(g);
+      return set_error(DITR_EINVAL, "no partition plan fits %lld nodes per workgroup",
+                       (long long)cap_nodes);
+    }
+    int64_t need = (n + (cap_nodes * 3 / 4) - 1) / std::max<int64_t>(1, cap_nodes * 3 / 4);
+    K = std::min<int64_t>(n, std::max<int64_t>(2 * K, need));
+  }
+  rc = build_part_plan(c, g);
+  if (rc) {
+    ditr_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return DITR_OK;
+}
+
+int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, int64_t cap) {
+  if (!g || !K_out) return set_error(DITR_EINVAL, "NULL argument");
+  *K_out = g->K;
+  if (h_ptr) {
+    if (cap < g->K + 1) return set_error(DITR_EINVAL, "cap < K + 1");
+    memcpy(h_ptr, g->part_ptr_host, sizeof(int64_t) * (g->K + 1));
+  }
+  return DITR_OK;
+}
+
+int ditr_residual(ditr_ctx* c, const ditr_graph* g, const double* d_b, const double* d_h,
+                  float* d_f, double* h_resid) {
+  if (!c || !g || !d_b || !d_h || !d_f) return set_error(DITR_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(c->device));
+  int rc = launch_refresh(c, g, d_b, d_h, d_f);
+  if (rc) return rc;
+  if (h_resid) {
+    rc = read_ctrl(c);
+    if (rc) return rc;
+    *h_resid = c->ctrl_host->sum_abs;
+  }
+  return DITR_OK;
+}
+
+int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
+               int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats) {
+  const double t0 = now_s();
+  ditr_stats st;
+  memset(&st, 0, sizeof(st));
+  auto finish = [&](int status) {
+    st.status = status;
+    st.seconds = now_s() - t0;
+    if (stats) *stats = st;
+    return status;
+  };
+  if (!c || !g || !d_b || !d_h || !d_f) return finish(set_error(DITR_EINVAL, "NULL argument"));
+  if (!(rel_tol >= 0) || !std::isfinite(rel_tol)) return finish(set_error(DITR_EINVAL, "rel_tol must be >= 0"));
+  ditr_opts o;
+  ditr_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.alpha > 1)) return finish(set_error(DITR_EINVAL, "alpha must be > 1"));
+  if (o.block == 0) o.block = 1024;
+  if (o.max_rounds <= 0) o.max_rounds = 16;
+  HIP_TRY(hipSetDevice(c->device));
+  __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
+  const int64_t n = g->n;
+
+  int rc = launch_reset_ctrl(c);
+  if (rc) return finish(rc);
+  double b1 = 0, r = 0, fmax = 0;
+  if (!warm) {
+    // F = B, H = 0; ||B||_1, ||F_0||_1 and max |F_0| in one pass
+    rc = launch_init(c, n, d_b, d_h, d_f);
+    if (!rc) rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    if (c->ctrl_host->err) return finish(set_error(DITR_ENONFINITE, "B holds NaN or Inf"));
+    b1 = c->ctrl_host->sum_abs;
+    r = c->ctrl_host->sum_abs_f32;
+    fmax = c->ctrl_host->max_abs;
+  } else {
+    // warm start / resume: F_0 = B + P H_0 - H_0 (identity of equations defF and defH)
+    rc = launch_norm_f64(c, n, d_b);
+    if (!rc) rc = launch_check_finite(c, n, d_h);
+    if (!rc) rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    if (c->ctrl_host->err) return finish(set_error(DITR_ENONFINITE, "B or H_0 holds NaN or Inf"));
+    b1 = c->ctrl_host->sum_abs;
+    rc = launch_refresh(c, g, d_b, d_h, d_f);
+    if (!rc) rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    r = c->ctrl_host->sum_abs;
+    fmax = c->ctrl_host->max_abs;
+    st.refreshes += 1;
+  }
+  st.b_l1 = b1;
+  const double target = rel_tol * b1;
+  bool refreshed = warm != 0;
+
+  // persistent plan: static binding when every partition gets its own resident workgroup
+  PersistentCfg cfg;
+  memset(&cfg, 0, sizeof(cfg));
+  int mode = o.mode;
+  if (mode == DITR_MODE_AUTO) mode = DITR_MODE_PARTITION;
+  if (mode != DITR_MODE_ASYNC && mode != DITR_MODE_SWEEP && mode != DITR_MODE_PARTITION)
+    return finish(set_error(DITR_EINVAL, "unknown mode %d", mode));
+  if (mode == DITR_MODE_ASYNC) {
+    cfg.block = o.block;
+    cfg.lds_nodes = std::max<int>(1, g->max_part);
+    cfg.lds_bytes = lds_bytes_for(cfg.lds_nodes);
+    int per_cu = 0;
+    rc = persistent_occupancy(c, cfg.block, cfg.lds_bytes, &per_cu);
+    if (rc) return finish(rc);
+    if (per_cu < 1)
+      return finish(set_error(DITR_EINVAL, "persistent kernel does not fit a CU (block %d, LDS %zu)",
+                              cfg.block, cfg.lds_bytes));
+    const int wpc = o.wg_per_cu > 0 ? std::min(o.wg_per_cu, per_cu) : per_cu;
+    const int64_t resident = (int64_t)c->num_cus * wpc;
+    cfg.static_mode = g->K <= resident;
+    cfg.grid = (int)(cfg.static_mode ? g->K : resident);
+    cfg.max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 1 << 20;
+    cfg.sweeps_per_claim = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
+    cfg.max_passes = (int)std::max<int64_t>(1, std::min<int64_t>(100000, ((int64_t)1 << 30) / g->K));
+    cfg.xcd_remap = o.xcd_remap;
+    cfg.alpha = o.alpha;
+    cfg.park_ratio = o.park_ratio;
+    cfg.rescale_cap = o.rescale_cap > 1 ? o.rescale_cap : 1.0;
+  }
+
+  int status = DITR_OK;
+  double t_carry = 0;
+  while (r > target) {
+    if (st.rounds >= o.max_rounds) {
+      status = DITR_NOT_CONVERGED;
+      break;
+    }
+    if (__atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) {
+      status = DITR_ABORTED;
+      break;
+    }
+    // stage 1 stops at refresh_at ||B||_1, where the exact residual replaces the
+    // FP32 fluid and its rounding drift; later stages aim below the target
+    const double stage = (!refreshed && r > o.refresh_at * b1) ? std::max(target, o.refresh_at * b1)
+                                                               : 0.5 * target;
+    // the threshold continues from the previous round (never above max|F| / alpha)
+    const double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha) : fmax / o.alpha;
+    rc = launch_set_launch_target(c, r, stage, T0);
+    if (rc) return finish(rc);
+    if (mode == DITR_MODE_PARTITION) {
+      // launches of m local sweeps in batches; the stop flag turns the rest of a batch into no-ops
+      rc = launch_part_prepare(c, g);
+      if (rc) return finish(rc);
+      const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
+      const int batch = 8;
+      const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
+      for (int64_t done_l = 0; done_l < budget; done_l += batch) {
+        rc = launch_part_sweeps(c, g, d_f, d_h, o.alpha, m, batch);
+        if (!rc) rc = read_ctrl(c);
+        if (rc) return finish(rc);
+        st.launches += batch;
+        if (c->ctrl_host->done || __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) break;
+      }
+    } else if (mode == DITR_MODE_ASYNC) {
+      if (!cfg.static_mode) {
+        rc = launch_fill_double(c, g->part_T, g->K, -1.0);
+        if (rc) return finish(rc);
+      }
+      rc = launch_persistent(c, g, d_f, d_h, cfg);
+      if (rc) return finish(rc);
+      st.launches += 1;
+    } else {
+      // pull sweeps in batches; the stop flag turns the rest of a batch into no-ops
+      rc = launch_pull_prepare(c, g);
+      if (rc) return finish(rc);
+      const int batch = 16;
+      const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
+      for (int64_t done_sweeps = 0; done_sweeps < budget; done_sweeps += batch) {
+        rc = launch_pull_sweeps(c, g, d_f, d_h, o.alpha, 0, batch);
+        if (!rc) rc = read_ctrl(c);
+        if (rc) return finish(rc);
+        st.launches += batch;
+        if (c->ctrl_host->done || __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) break;
+      }
+    }
+    rc = launch_refresh(c, g, d_b, d_h, d_f);
+    if (!rc) rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    st.refreshes += 1;
+    st.rounds += 1;
+    refreshed = true;
+    t_carry = c->ctrl_host->T;
+    r = c->ctrl_host->sum_abs;
+    fmax = c->ctrl_host->max_abs;
+    if (!std::isfinite(r)) return finish(set_error(DITR_ENONFINITE, "residual became non-finite"));
+  }
+  if (status == DITR_OK && __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST) && r > target)
+    status = DITR_ABORTED;
+  st.edges = (int64_t)c->ctrl_host->edges;
+  st.diffusions = (int64_t)c->ctrl_host->diffusions;
+  st.sweeps = (int64_t)c->ctrl_host->sweeps;
+  st.idle_polls = (int64_t)c->ctrl_host->idle_polls;
+  st.resid_l1 = r;
+  if (status == DITR_NOT_CONVERGED)
+    set_error(status, "not converged after %d rounds (||F||_1 = %g, target %g)", st.rounds, r, target);
+  return finish(status);
+}
+
+}  // extern "C"

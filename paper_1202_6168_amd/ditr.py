@@ -1,0 +1,248 @@
+"""Thin Python binding of the ditr C-ABI (include/ditr.h).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+libditr.so. PyTorch supplies device memory (tensors) and the stream. There is
+no CPU fallback: if the library is missing, importing the binding raises.
+
+Functions keep the C names without the ``ditr_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libditr.so")
+
+OK, NOT_CONVERGED, ABORTED = 0, 1, 2
+EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
+PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
+MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
+
+_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "ABORTED", -1: "EINVAL", -2: "EGRAPH",
+                 -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE"}
+
+
+class DitrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (_STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double),
+        ("refresh_at", ctypes.c_double),
+        ("park_ratio", ctypes.c_double),
+        ("rescale_cap", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("part_type", ctypes.c_int32),
+        ("part_nodes", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("wg_per_cu", ctypes.c_int32),
+        ("sweeps_per_claim", ctypes.c_int32),
+        ("max_rounds", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32),
+        ("xcd_remap", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("edges", ctypes.c_int64),
+        ("diffusions", ctypes.c_int64),
+        ("sweeps", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+        ("refreshes", ctypes.c_int64),
+        ("idle_polls", ctypes.c_int64),
+        ("resid_l1", ctypes.c_double),
+        ("b_l1", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("rounds", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+_vp, _i64, _i32, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+_SIGNATURES = {
+    "ditr_version": ([], _i32),
+    "ditr_last_error": ([], ctypes.c_char_p),
+    "ditr_opts_default": ([ctypes.POINTER(Opts)], _i32),
+    "ditr_create": ([ctypes.POINTER(_vp), _i32, _vp], _i32),
+    "ditr_destroy": ([_vp], _i32),
+    "ditr_abort": ([_vp], _i32),
+    "ditr_graph_create": ([_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _dbl,
+                           ctypes.POINTER(Opts)], _i32),
+    "ditr_graph_destroy": ([_vp], _i32),
+    "ditr_graph_partitions": ([_vp, ctypes.POINTER(_i64), _vp, _i64], _i32),
+    "ditr_partition": ([_vp, _i64, _i64, _vp, _vp, _i32, _i64, _vp], _i32),
+    "ditr_residual": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)], _i32),
+    "ditr_solve": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
+                    ctypes.POINTER(Stats)], _i32),
+}
+
+
+def lib():
+    """Load libditr.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libditr.so is not built: run __graft_entry__.build() "
+                                   "(no CPU fallback exists)")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (args, res) in _SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = res
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    m = lib().ditr_last_error()
+    return m.decode(errors="replace") if m else ""
+
+
+def check(status: int, allow=(OK,)) -> int:
+    if status not in allow:
+        raise DitrError(status, last_error())
+    return status
+
+
+def version() -> int:
+    return lib().ditr_version()
+
+
+def opts_default(**overrides) -> Opts:
+    o = Opts()
+    check(lib().ditr_opts_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """ditr_ctx on one device, issuing work on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.device = device
+        self.torch = torch
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(torch, device)
+        h = ctypes.c_void_p()
+        check(lib().ditr_create(ctypes.byref(h), device, s))
+        self.handle = h
+
+    def abort(self):
+        check(lib().ditr_abort(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().ditr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """ditr_graph: borrows the CSC tensors (int32, on the context's device)."""
+
+    def __init__(self, ctx: Context, col_ptr, row_idx, damping: float = 0.85, opts: Opts = None):
+        torch = ctx.torch
+        if col_ptr.dtype != torch.int32 or row_idx.dtype != torch.int32:
+            raise TypeError("CSC arrays must be int32")
+        if not (col_ptr.is_cuda and row_idx.is_cuda):
+            raise TypeError("CSC arrays must be device tensors")
+        self.ctx = ctx
+        self.col_ptr = col_ptr.contiguous()
+        self.row_idx = row_idx.contiguous()
+        self.n = self.col_ptr.numel() - 1
+        self.nnz = self.row_idx.numel()
+        h = ctypes.c_void_p()
+        o = opts if opts is not None else opts_default()
+        check(lib().ditr_graph_create(ctx.handle, ctypes.byref(h), self.n, self.nnz,
+                                      _ptr(self.col_ptr), _ptr(self.row_idx) if self.nnz else None,
+                                      damping, ctypes.byref(o)))
+        self.handle = h
+
+    def partitions(self):
+        import numpy as np
+
+        K = ctypes.c_int64()
+        check(lib().ditr_graph_partitions(self.handle, ctypes.byref(K), None, 0))
+        out = np.empty(K.value + 1, np.int64)
+        check(lib().ditr_graph_partitions(self.handle, ctypes.byref(K),
+                                          ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().ditr_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def partition(ctx: Context, col_ptr, part_type: int, K: int, out, row_idx=None):
+    """ditr_partition: K+1 boundaries (int64 device tensor `out`)."""
+    nnz = row_idx.numel() if row_idx is not None else 0
+    check(lib().ditr_partition(ctx.handle, col_ptr.numel() - 1, nnz, _ptr(col_ptr),
+                               _ptr(row_idx) if row_idx is not None else None, part_type, K,
+                               _ptr(out)))
+    return out
+
+
+def residual(ctx: Context, g: Graph, b, h, f, want_norm: bool = True):
+    """ditr_residual: F = B + P H - H (FP64 arithmetic, FP32 store); returns ||F||_1."""
+    r = ctypes.c_double()
+    check(lib().ditr_residual(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f),
+                              ctypes.byref(r) if want_norm else None))
+    return r.value if want_norm else None
+
+
+def solve(ctx: Context, g: Graph, b, h, f, warm: bool = False, rel_tol: float = 1e-9,
+          opts: Opts = None, allow=(OK, NOT_CONVERGED, ABORTED)) -> Stats:
+    """ditr_solve: diffuse until the exact ||F||_1 <= rel_tol ||B||_1."""
+    torch = ctx.torch
+    if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
+        raise TypeError("b, h must be float64 and f float32")
+    for t in (b, h, f):
+        if t.numel() != g.n or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("b, h, f must be contiguous device vectors of length n")
+    st = Stats()
+    o = opts if opts is not None else opts_default()
+    rc = lib().ditr_solve(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f), int(bool(warm)),
+                          rel_tol, ctypes.byref(o), ctypes.byref(st))
+    check(rc, allow)
+    return st

@@ -1,0 +1,301 @@
+"""GPU parity of the plain solve against the FP64 oracle (through the C-ABI).
+
+Several H are correct (the diffusion order is free, Section 2), so H is not
+compared bit for bit: every valid run satisfies ||X - H||_1 <= ||F||_1/(1-d)
+(Section 2, the bound after defH), hence
+    ||H_gpu - H_oracle||_1 <= (tol_gpu + tol_oracle) ||B||_1 / (1 - d),
+and the headline requirement ||H_gpu - H_oracle||_1 <= 1e-6 ||H_oracle||_1.
+The returned F must be the exact residual B + P H - H (rounded to FP32).
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import ditgen
+import oracle
+from conftest import D, csc_from_edges, random_graph, sparse_p
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1202_6168_amd import ditr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ditr.Context(0)
+    yield c
+    c.close()
+
+
+def upload(cp, ri):
+    dev = torch.device("cuda", 0)
+    return (torch.from_numpy(np.ascontiguousarray(cp, np.int32)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(ri, np.int32)).to(dev) if ri.size else
+            torch.zeros(1, dtype=torch.int32, device=dev)[:0])
+
+
+def gpu_solve(ctx, cp, ri, b, tol, h0=None, **opt):
+    g = ditr.Graph(ctx, *upload(cp, ri), opts=ditr.opts_default(**{k: v for k, v in opt.items()
+                                                                    if k in ("part_nodes", "part_type", "block", "wg_per_cu")}))
+    dev = torch.device("cuda", 0)
+    bt = torch.from_numpy(np.ascontiguousarray(b, np.float64)).to(dev)
+    ht = (torch.from_numpy(np.ascontiguousarray(h0, np.float64)).to(dev) if h0 is not None
+          else torch.empty(len(b), dtype=torch.float64, device=dev))
+    ft = torch.empty(len(b), dtype=torch.float32, device=dev)
+    st = ditr.solve(ctx, g, bt, ht, ft, warm=h0 is not None, rel_tol=tol,
+                    opts=ditr.opts_default(**opt))
+    torch.cuda.synchronize()
+    out = ht.cpu().numpy(), ft.cpu().numpy().astype(np.float64), st
+    g.close()
+    return out
+
+
+def check_parity(cp, ri, b, h, f, st, tol, ref=None, ref_tol=1e-13):
+    """Bound-based parity with the oracle + the identity on the returned F."""
+    ref = ref if ref is not None else oracle.solve(cp, ri, b, rel_tol=ref_tol)
+    b1 = np.abs(b).sum()
+    assert st.status == ditr.OK, ditr.last_error()
+    assert st.resid_l1 <= tol * b1 * (1 + 1e-12)
+    err = np.abs(h - ref.h).sum()
+    assert err <= (st.resid_l1 + ref.resid_l1) / (1 - D) * (1 + 1e-6) + 1e-300
+    assert err <= 1e-6 * np.abs(ref.h).sum() + 1e-300
+    ident = b + sparse_p(cp, ri) @ h - h
+    scale = np.abs(b).sum() + np.abs(h).sum()
+    assert np.abs(f - ident).sum() <= 1e-7 * np.abs(ident).sum() + 1e-14 * scale
+    assert abs(np.abs(f).sum() - st.resid_l1) <= 1e-6 * st.resid_l1 + 1e-14 * scale
+    return ref
+
+
+# ---------------------------------------------------------------------------
+# adversarial small graphs, every kernel mode and forced tiny partitions
+
+def _adversarial():
+    cases = []
+    n = 257
+    cases.append(("hub_in", *csc_from_edges(n, [(i, 0) for i in range(1, n)] + [(0, 5)])))
+    cases.append(("hub_out", *csc_from_edges(n, [(0, j) for j in range(1, n)])))
+    cases.append(("loops_multi", *random_graph(150, np.random.default_rng(7), 0.05, True, True)))
+    cases.append(("all_dangling", np.zeros(101, np.int32), np.zeros(0, np.int32)))
+    cases.append(("single_node", np.zeros(2, np.int32), np.zeros(0, np.int32)))
+    cases.append(("single_loop", *csc_from_edges(1, [(0, 0)])))
+    edges = [(i, (i + 1) % 999) for i in range(3, 990)]  # empty columns at both ends
+    cases.append(("empty_ends", *csc_from_edges(999, edges)))
+    cases.append(("cycle", *csc_from_edges(1000, [(i, (i + 1) % 1000) for i in range(1000)])))
+    return cases
+
+
+ADV = _adversarial()
+
+
+@pytest.mark.parametrize("case", ADV, ids=[c[0] for c in ADV])
+@pytest.mark.parametrize("mode,part_nodes,block", [
+    (ditr.MODE_PARTITION, 0, 1024),
+    (ditr.MODE_PARTITION, 3, 1024),  # tiny partitions: nearly every link crosses
+    (ditr.MODE_PARTITION, 64, 1024),
+    (ditr.MODE_ASYNC, 0, 1024),
+    (ditr.MODE_ASYNC, 3, 256),
+    (ditr.MODE_ASYNC, 16, 512),
+    (ditr.MODE_SWEEP, 0, 1024),
+])
+def test_adversarial_parity(ctx, case, mode, part_nodes, block):
+    name, cp, ri = case
+    n = cp.size - 1
+    rng = np.random.default_rng(n)
+    b = rng.uniform(0.1, 1.0, n) / n
+    tol = 1e-10
+    h, f, st = gpu_solve(ctx, cp, ri, b, tol, mode=mode, part_nodes=part_nodes, block=block)
+    check_parity(cp, ri, b, h, f, st, tol)
+
+
+def test_closed_forms(ctx):
+    # one edge 0 -> 1
+    cp, ri = csc_from_edges(2, [(0, 1)])
+    b = np.array([0.3, 0.5])
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-12)
+    assert np.abs(h - [0.3, 0.5 + D * 0.3]).max() < 1e-12
+    # star: hub -> k dangling leaves
+    k = 40
+    cp, ri = csc_from_edges(k + 1, [(0, j) for j in range(1, k + 1)])
+    b = np.linspace(0.1, 0.7, k + 1)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-12, part_nodes=4)
+    want = b.copy()
+    want[1:] += D * b[0] / k
+    assert np.abs(h - want).max() < 1e-12
+    # directed cycle, uniform B: x = b / (1 - d)
+    n = 5000
+    cp, ri = csc_from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+    h, f, st = gpu_solve(ctx, cp, ri, np.full(n, 0.2), 1e-11)
+    assert np.abs(h - 0.2 / (1 - D)).sum() <= st.resid_l1 / (1 - D) * (1 + 1e-6) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# the workload graphs
+
+@pytest.mark.parametrize("mode", [ditr.MODE_PARTITION, ditr.MODE_ASYNC, ditr.MODE_SWEEP])
+def test_small_workload_parity(ctx, mode):
+    """1e4 nodes, block-100 locality, tolerance 1e-12 ||B||_1."""
+    spec = ditgen.SMALL
+    cp, ri = ditgen.generate(spec)
+    b = ditgen.uniform_b(spec.n)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-12, mode=mode)
+    check_parity(cp, ri, b, h, f, st, 1e-12, ref_tol=1e-14)
+    assert st.edges > 0 and st.diffusions > 0
+
+
+@pytest.fixture(scope="module")
+def headline():
+    spec = ditgen.HEADLINE
+    cp, ri = ditgen.generate(spec)
+    b = ditgen.uniform_b(spec.n)
+    ref = oracle.solve(cp, ri, b, rel_tol=1e-12)
+    return cp, ri, b, ref
+
+
+@pytest.mark.parametrize("mode", [ditr.MODE_PARTITION, ditr.MODE_ASYNC, ditr.MODE_SWEEP])
+def test_headline_parity(ctx, headline, mode):
+    """1e6 nodes, ~8e6 edges, tolerance 1e-9 ||B||_1; H within 1e-6 relative L1."""
+    cp, ri, b, ref = headline
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-9, mode=mode)
+    check_parity(cp, ri, b, h, f, st, 1e-9, ref=ref)
+    # D-iteration's cost stays well below power iteration's 128 L at 1e-9
+    assert st.edges < 128 * ri.size
+
+
+def test_repeat_runs_within_parity(ctx, headline):
+    """Runs may differ (float atomics); every run must stay within parity."""
+    cp, ri, b, ref = headline
+    hs = []
+    for _ in range(3):
+        h, f, st = gpu_solve(ctx, cp, ri, b, 1e-9)
+        check_parity(cp, ri, b, h, f, st, 1e-9, ref=ref)
+        hs.append(h)
+    assert np.abs(hs[0] - hs[1]).sum() <= 2 * 1e-9 * b.sum() / (1 - D) * 1.01
+
+
+@pytest.mark.parametrize("ptype", [ditr.PART_CB, ditr.PART_UNIFORM, ditr.PART_CB_INOUT])
+@pytest.mark.parametrize("part_nodes,m", [(500, 1), (2000, 2), (6000, 8)])
+def test_partition_mode_settings(ctx, ptype, part_nodes, m):
+    spec = ditgen.GraphSpec(n=60_000, block=1000, seed=31)
+    cp, ri = ditgen.generate(spec)
+    b = ditgen.uniform_b(spec.n)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-10, mode=ditr.MODE_PARTITION, part_type=ptype,
+                         part_nodes=part_nodes, sweeps_per_claim=m)
+    check_parity(cp, ri, b, h, f, st, 1e-10)
+
+
+def test_warm_start_parity(ctx):
+    spec = ditgen.GraphSpec(n=50_000, block=1000, seed=17)
+    cp, ri = ditgen.generate(spec)
+    b = ditgen.uniform_b(spec.n)
+    ref = oracle.solve(cp, ri, b, rel_tol=1e-13)
+    h0 = ref.h * np.random.default_rng(1).uniform(0.7, 1.3, spec.n)  # signed F_0
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-10, h0=h0)
+    check_parity(cp, ri, b, h, f, st, 1e-10, ref=ref)
+    # resume: a finished H restarts with nothing to do
+    h2, f2, st2 = gpu_solve(ctx, cp, ri, b, 1e-10, h0=h)
+    assert st2.edges == 0 and np.array_equal(h2, h)
+
+
+# ---------------------------------------------------------------------------
+# partition plan and exact residual kernels
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 64, 256, 1000])
+@pytest.mark.parametrize("ptype", [ditr.PART_CB, ditr.PART_UNIFORM, ditr.PART_CB_INOUT])
+def test_partition_bit_exact(ctx, K, ptype):
+    spec = ditgen.GraphSpec(n=100_000, block=1000, seed=2)
+    cp, ri = ditgen.generate(spec)
+    out = torch.empty(K + 1, dtype=torch.int64, device="cuda")
+    cpt, rit = upload(cp, ri)
+    ditr.partition(ctx, cpt, ptype, K, out, row_idx=rit)
+    want = {ditr.PART_CB: lambda: oracle.partition_cb(cp, K),
+            ditr.PART_UNIFORM: lambda: oracle.partition_uniform(spec.n, K),
+            ditr.PART_CB_INOUT: lambda: oracle.partition_cb_inout(cp, ri, K)}[ptype]()
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("ptype", [ditr.PART_CB, ditr.PART_CB_INOUT, ditr.PART_UNIFORM])
+def test_graph_plan_matches_oracle(ctx, ptype):
+    spec = ditgen.GraphSpec(n=200_000, block=1000, seed=4)
+    cp, ri = ditgen.generate(spec)
+    g = ditr.Graph(ctx, *upload(cp, ri), opts=ditr.opts_default(part_type=ptype))
+    ptr = g.partitions()
+    K = len(ptr) - 1
+    want = {ditr.PART_CB: lambda: oracle.partition_cb(cp, K),
+            ditr.PART_UNIFORM: lambda: oracle.partition_uniform(spec.n, K),
+            ditr.PART_CB_INOUT: lambda: oracle.partition_cb_inout(cp, ri, K)}[ptype]()
+    assert np.array_equal(ptr, want)
+    g.close()
+
+
+def test_residual_matches_oracle(ctx):
+    rng = np.random.default_rng(9)
+    spec = ditgen.GraphSpec(n=30_000, block=1000, seed=9)
+    cp, ri = ditgen.generate(spec)
+    # add a heavy in-degree row to exercise the per-row workgroup path
+    cp2, ri2 = csc_from_edges(spec.n, [(s, t) for s in range(spec.n)
+                                       for t in ri[cp[s]:cp[s + 1]]] + [(s, 7) for s in range(0, spec.n, 10) if s != 7])
+    for (c, r) in [(cp, ri), (cp2, ri2)]:
+        b = rng.uniform(0, 1e-4, spec.n)
+        h = rng.uniform(0, 1e-3, spec.n) * (rng.random(spec.n) < 0.9)
+        g = ditr.Graph(ctx, *upload(c, r))
+        dev = torch.device("cuda", 0)
+        bt, ht = torch.from_numpy(b).to(dev), torch.from_numpy(h).to(dev)
+        ft = torch.empty(spec.n, dtype=torch.float32, device=dev)
+        r1 = ditr.residual(ctx, g, bt, ht, ft)
+        want = oracle.fluid_from_history(c, r, b, h)
+        got = ft.cpu().numpy().astype(np.float64)
+        scale = np.abs(b) + np.abs(h) + np.abs(sparse_p(c, r)) @ np.abs(h)
+        assert np.all(np.abs(got - want) <= 2.0 ** -24 * np.abs(want) + 1e-15 * scale)
+        assert abs(r1 - np.abs(want).sum()) <= 1e-12 * scale.sum()
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# errors and abort
+
+def test_errors(ctx):
+    dev = torch.device("cuda", 0)
+    cp = torch.tensor([0, 1, 1], dtype=torch.int32, device=dev)
+    bad = torch.tensor([5], dtype=torch.int32, device=dev)
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.Graph(ctx, cp, bad)
+    assert e.value.status == ditr.EGRAPH
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.Graph(ctx, torch.tensor([0, 2, 1], dtype=torch.int32, device=dev),
+                   torch.tensor([0, 1], dtype=torch.int32, device=dev))
+    assert e.value.status == ditr.EGRAPH
+    ok = torch.tensor([0], dtype=torch.int32, device=dev)
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.Graph(ctx, cp, ok, damping=1.0)
+    assert e.value.status == ditr.EINVAL
+    g = ditr.Graph(ctx, cp, ok)
+    b = torch.tensor([1.0, float("nan")], dtype=torch.float64, device=dev)
+    h = torch.empty(2, dtype=torch.float64, device=dev)
+    f = torch.empty(2, dtype=torch.float32, device=dev)
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.solve(ctx, g, b, h, f)
+    assert e.value.status == ditr.ENONFINITE
+    g.close()
+
+
+def test_abort_keeps_identity(ctx, headline):
+    cp, ri, b, ref = headline
+    g = ditr.Graph(ctx, *upload(cp, ri))
+    dev = torch.device("cuda", 0)
+    bt = torch.from_numpy(b).to(dev)
+    ht = torch.empty(len(b), dtype=torch.float64, device=dev)
+    ft = torch.empty(len(b), dtype=torch.float32, device=dev)
+    t = threading.Timer(0.0005, ctx.abort)
+    t.start()
+    st = ditr.solve(ctx, g, bt, ht, ft, rel_tol=1e-14, opts=ditr.opts_default(max_rounds=64))
+    t.join()
+    assert st.status in (ditr.OK, ditr.ABORTED, ditr.NOT_CONVERGED)
+    h, f = ht.cpu().numpy(), ft.cpu().numpy().astype(np.float64)
+    ident = b + sparse_p(cp, ri) @ h - h
+    assert np.abs(f - ident).sum() <= 1e-7 * np.abs(ident).sum() + 1e-14 * np.abs(h).sum()
+    g.close()

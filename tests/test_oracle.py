@@ -240,6 +240,45 @@ def test_partition_cb_nested():
     assert set(p4.tolist()) <= set(p8.tolist())
 
 
+@pytest.mark.parametrize("K", [1, 3, 16, 100])
+def test_partition_cb_inout_balance(K):
+    """In+out cost per block within the largest in+out degree of 2L/K, and each
+    boundary is the first id whose in+out prefix reaches k 2L/K."""
+    spec = ditgen.GraphSpec(n=20_000, block=1000, seed=6)
+    cp, ri = ditgen.generate(spec)
+    ptr = oracle.partition_cb_inout(cp, ri, K)
+    indeg = np.bincount(ri, minlength=spec.n)
+    cost = np.concatenate([[0], np.cumsum(np.diff(cp) + indeg)])
+    L2 = int(cost[-1])
+    maxdeg = int((np.diff(cp) + indeg).max())
+    blocks = cost[ptr[1:]] - cost[ptr[:-1]]
+    assert np.all(np.abs(blocks - L2 / K) <= maxdeg)
+    for k in range(1, K):
+        j = int(ptr[k])
+        assert K * int(cost[j]) >= k * L2 and (j == 0 or K * int(cost[j - 1]) < k * L2)
+    # hubs have large in-degree: the first block holds fewer ids than under CB
+    if K >= 16:
+        assert ptr[1] < oracle.partition_cb(cp, K)[1]
+
+
+def test_partition_cb_inout_special_cases():
+    # 1-regular both ways: in+out balance is the uniform split
+    n = 24
+    cp, ri = csc_from_edges(n, [(i, (i + 5) % n) for i in range(n)])
+    assert oracle.partition_cb_inout(cp, ri, 6).tolist() == oracle.partition_uniform(n, 6).tolist()
+    # symmetric graph: in-link prefix = out-link prefix, so CB_INOUT = CB
+    rng = np.random.default_rng(8)
+    und = set()
+    for _ in range(300):
+        a, b = rng.integers(0, 60, 2)
+        if a != b:
+            und.add((int(a), int(b)))
+            und.add((int(b), int(a)))
+    cp, ri = csc_from_edges(60, sorted(und))
+    for K in (2, 5, 9):
+        assert oracle.partition_cb_inout(cp, ri, K).tolist() == oracle.partition_cb(cp, K).tolist()
+
+
 def test_rejects_bad_input():
     cp = np.array([0, 1], np.int32)
     ri = np.array([3], np.int32)

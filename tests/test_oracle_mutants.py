@@ -32,6 +32,9 @@ MUTANTS = {
     "transposed_identity": ("for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += p * h[i];",
                             "for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[i] += p * h[row_idx[e]];"),
     "cb_off_by_one": ("(int64_t)col_ptr[j] * K < k * L", "(int64_t)col_ptr[j] * K <= k * L"),
+    "inout_drops_in_links": ("for (int64_t e = 0; e < nnz; ++e) cost[row_idx[e] + 1] += 1;",
+                             "for (int64_t e = 0; e < 0; ++e) cost[row_idx[e] + 1] += 1;"),
+    "inout_in_links_shifted": ("cost[row_idx[e] + 1] += 1;", "cost[row_idx[e]] += 1;"),
 }
 
 
@@ -97,6 +100,15 @@ def pin_suite(lib):
     ccp, _ = csc_from_edges(16, [(i, (i + 1) % 16) for i in range(16)])
     if oracle.partition_cb(ccp, 4, lib=lib).tolist() != [0, 4, 8, 12, 16]:
         fails.append("cb_regular")
+    # in+out balance against the definition (in-links counted independently)
+    indeg = np.bincount(gri, minlength=spec.n)
+    cost = np.concatenate([[0], np.cumsum(np.diff(gcp) + indeg)])
+    pio = oracle.partition_cb_inout(gcp, gri, 8, lib=lib)
+    for k in range(1, 8):
+        j = int(pio[k])
+        if not (8 * int(cost[j]) >= k * int(cost[-1]) and (j == 0 or 8 * int(cost[j - 1]) < k * int(cost[-1]))):
+            fails.append("cb_inout")
+            break
     K, L = 8, int(gcp[-1])
     ptr = oracle.partition_cb(gcp, K, lib=lib)
     for k in range(1, K):
