@@ -87,8 +87,12 @@ typedef struct {
   int32_t max_rounds;  /* persistent launches (each followed by an exact residual) */
   int32_t max_sweeps;  /* sweep budget per launch and workgroup (0 = auto) */
   int32_t xcd_remap;   /* 1: place neighbouring partitions on the same XCD */
-  uint32_t flags;      /* reserved, 0 */
+  uint32_t flags;      /* DITR_FLAG_* bits */
 } ditr_opts;
+
+/* opts.flags: time every diffusion launch with HIP events on the context's
+ * stream and report the sum in ditr_stats.kernel_seconds. */
+#define DITR_FLAG_TIME_KERNELS 1u
 
 typedef struct {
   int64_t edges;       /* elementary edge diffusions (Section 2.4: normalized iterations x L) */
@@ -100,6 +104,8 @@ typedef struct {
   double resid_l1;     /* final exact ||F||_1 (FP64, from the last refresh) */
   double b_l1;         /* ||B||_1 */
   double seconds;      /* host wall time of the call */
+  double kernel_seconds;  /* with DITR_FLAG_TIME_KERNELS: event-timed diffusion launches */
+  int64_t timed_launches; /* launches covered by kernel_seconds */
   int32_t rounds;      /* outer rounds used */
   int32_t status;      /* same as the return value */
 } ditr_stats;

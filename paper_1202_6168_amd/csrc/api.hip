@@ -412,6 +412,46 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     cfg.rescale_cap = o.rescale_cap > 1 ? o.rescale_cap : 1.0;
   }
 
+  // optional event timing of the diffusion launches (partitioned sweep: each
+  // launch of its main kernel; other modes: each batch)
+  const bool timed = (o.flags & DITR_FLAG_TIME_KERNELS) != 0;
+  constexpr int kBatch = 8;
+  hipEvent_t ev[2 * kBatch] = {};
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 2 * kBatch; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } ev_guard{ev};
+  if (timed)
+    for (int i = 0; i < 2 * kBatch; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+  auto t_begin = [&]() -> int {
+    if (timed) HIP_TRY(hipEventRecord(ev[0], c->stream));
+    return DITR_OK;
+  };
+  auto t_end = [&](int64_t launches) -> int {
+    if (!timed) return DITR_OK;
+    HIP_TRY(hipEventRecord(ev[1], c->stream));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    st.kernel_seconds += 1e-3 * ms;
+    st.timed_launches += launches;
+    return DITR_OK;
+  };
+  // sum the first `executed` launch intervals of a batch (later ones were no-ops)
+  auto t_sum = [&](int64_t executed) -> int {
+    if (!timed) return DITR_OK;
+    for (int64_t i = 0; i < executed && i < kBatch; ++i) {
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+      st.kernel_seconds += 1e-3 * ms;
+      st.timed_launches += 1;
+    }
+    return DITR_OK;
+  };
+
   int status = DITR_OK;
   double t_carry = 0;
   while (r > target) {
@@ -436,11 +476,13 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       rc = launch_part_prepare(c, g);
       if (rc) return finish(rc);
       const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
-      const int batch = 8;
+      const int batch = kBatch;
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
       for (int64_t done_l = 0; done_l < budget; done_l += batch) {
-        rc = launch_part_sweeps(c, g, d_f, d_h, o.alpha, m, batch);
+        const uint64_t before = c->ctrl_host->sweeps;
+        rc = launch_part_sweeps(c, g, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr);
         if (!rc) rc = read_ctrl(c);
+        if (!rc) rc = t_sum((int64_t)(c->ctrl_host->sweeps - before));
         if (rc) return finish(rc);
         st.launches += batch;
         if (c->ctrl_host->done || __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) break;
@@ -450,7 +492,9 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
         rc = launch_fill_double(c, g->part_T, g->K, -1.0);
         if (rc) return finish(rc);
       }
-      rc = launch_persistent(c, g, d_f, d_h, cfg);
+      rc = t_begin();
+      if (!rc) rc = launch_persistent(c, g, d_f, d_h, cfg);
+      if (!rc) rc = t_end(1);
       if (rc) return finish(rc);
       st.launches += 1;
     } else {
@@ -460,7 +504,9 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       const int batch = 16;
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
       for (int64_t done_sweeps = 0; done_sweeps < budget; done_sweeps += batch) {
-        rc = launch_pull_sweeps(c, g, d_f, d_h, o.alpha, 0, batch);
+        rc = t_begin();
+        if (!rc) rc = launch_pull_sweeps(c, g, d_f, d_h, o.alpha, 0, batch);
+        if (!rc) rc = t_end(batch);
         if (!rc) rc = read_ctrl(c);
         if (rc) return finish(rc);
         st.launches += batch;

@@ -223,7 +223,7 @@ int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                       int nlaunch);
+                       int nlaunch, hipEvent_t* ev);
 struct PersistentCfg {
   int block;
   int grid;

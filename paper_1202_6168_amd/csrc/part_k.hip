@@ -710,7 +710,7 @@ int part_configure(ditr_ctx* c) {
 }
 
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                       int nlaunch) {
+                       int nlaunch, hipEvent_t* ev) {
   const PartPlan& q = g->pp;
   PartArgs a;
   a.n = g->n;
@@ -751,7 +751,9 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   const size_t lds = part_lds_bytes(a.lds_nodes, a.lds_edges);
   for (int s = 0; s < nlaunch; ++s) {
     if (q.n_chunks > 0) k_part_heavy<<<q.n_chunks, 256, 0, c->stream>>>(a, s & 1);
+    if (ev) HIP_TRY(hipEventRecord(ev[2 * s], c->stream));
     k_part_sweep<kPB><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+    if (ev) HIP_TRY(hipEventRecord(ev[2 * s + 1], c->stream));
   }
   HIP_TRY(hipGetLastError());
   return DITR_OK;

@@ -19,6 +19,7 @@ OK, NOT_CONVERGED, ABORTED = 0, 1, 2
 EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
 PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
+FLAG_TIME_KERNELS = 1
 
 _STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "ABORTED", -1: "EINVAL", -2: "EGRAPH",
                  -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE"}
@@ -63,6 +64,8 @@ class Stats(ctypes.Structure):
         ("resid_l1", ctypes.c_double),
         ("b_l1", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("kernel_seconds", ctypes.c_double),
+        ("timed_launches", ctypes.c_int64),
         ("rounds", ctypes.c_int32),
         ("status", ctypes.c_int32),
     ]
