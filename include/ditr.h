@@ -161,6 +161,20 @@ int ditr_residual(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, const d
 int ditr_solve(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
                int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats);
 
+/* ---- batched personalized PageRank (step: many right-hand sides) -------- */
+/* Diffuse nrhs right-hand sides at once (multiple of 4, 4..256), each to its
+ * own exact FP64 residual <= rel_tol * ||B_r||_1 (personalization vectors V of
+ * Section 2.2 in X = d Q X + (1-d) V). Node-major layouts with row stride nrhs:
+ * d_b FP64 [n][nrhs] (read), d_h FP64 [n][nrhs] (out: H, starts from 0),
+ * d_f FP32 [n][nrhs] (out: exact residual rounded to FP32). Every right-hand
+ * side has its own threshold T_r; all share each in-link read. per_rhs
+ * (nullable, [nrhs]) gets each right-hand side's residual, ||B_r||_1 and
+ * diffused edges; total (nullable) the sums and timing. Allocates a workspace
+ * of about 8 nrhs n bytes for the call. Synchronizes. */
+int ditr_solve_batched(ditr_ctx* ctx, const ditr_graph* g, int nrhs, const double* d_b,
+                       double* d_h, float* d_f, double rel_tol, const ditr_opts* opts,
+                       ditr_stats* per_rhs, ditr_stats* total);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,7 +101,8 @@ int ditr_create(ditr_ctx** out, int device, void* hip_stream) {
             hipHostGetDevicePointer((void**)&c->abort_dev, c->abort_host, 0) == hipSuccess &&
             hipMalloc((void**)&c->ctrl, sizeof(Ctrl)) == hipSuccess &&
             hipHostMalloc((void**)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) == hipSuccess &&
-            hipMalloc((void**)&c->partials, sizeof(double) * 4 * c->partials_cap) == hipSuccess;
+            hipMalloc((void**)&c->partials, sizeof(double) * 4 * c->partials_cap) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     ditr_destroy(c);
     return set_error(DITR_ENOMEM, "device or pinned allocation failed");
@@ -120,6 +121,7 @@ int ditr_destroy(ditr_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  if (c->work) (void)hipStreamDestroy(c->work);
   if (c->abort_host) (void)hipHostFree(c->abort_host);
   if (c->ctrl) (void)hipFree(c->ctrl);
   if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
@@ -534,6 +536,34 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   if (status == DITR_NOT_CONVERGED)
     set_error(status, "not converged after %d rounds (||F||_1 = %g, target %g)", st.rounds, r, target);
   return finish(status);
+}
+
+int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double* d_b, double* d_h,
+                       float* d_f, double rel_tol, const ditr_opts* opts, ditr_stats* per_rhs,
+                       ditr_stats* total) {
+  const double t0 = now_s();
+  if (!c || !g || !d_b || !d_h || !d_f) return set_error(DITR_EINVAL, "NULL argument");
+  if (!(rel_tol >= 0) || !std::isfinite(rel_tol)) return set_error(DITR_EINVAL, "rel_tol must be >= 0");
+  ditr_opts o;
+  ditr_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.alpha > 1)) return set_error(DITR_EINVAL, "alpha must be > 1");
+  HIP_TRY(hipSetDevice(c->device));
+  __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
+  int rc = launch_reset_ctrl(c);
+  if (!rc) rc = launch_check_finite(c, g->n * (int64_t)nrhs, d_b);
+  if (!rc) rc = read_ctrl(c);
+  if (rc) return rc;
+  if (c->ctrl_host->err) return set_error(DITR_ENONFINITE, "B holds NaN or Inf");
+  ditr_stats tot;
+  memset(&tot, 0, sizeof(tot));
+  rc = batch_solve(c, g, nrhs, d_b, d_h, d_f, rel_tol, o, per_rhs, &tot);
+  tot.seconds = now_s() - t0;
+  tot.status = rc;
+  if (total) *total = tot;
+  if (per_rhs && rc >= 0)
+    for (int r = 0; r < nrhs; ++r) per_rhs[r].seconds = tot.seconds;
+  return rc;
 }
 
 }  // extern "C"

@@ -29,6 +29,7 @@ struct Ctrl {
 struct ditr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t work = nullptr;  // private stream for graph-captured loops (default priority)
   int num_cus = 0;
   size_t lds_per_block = 0;    // default LDS limit of one workgroup
   size_t lds_per_cu = 0;       // LDS of one CU
@@ -243,3 +244,6 @@ int launch_persistent(ditr_ctx* c, const ditr_graph* g, float* f, double* h,
 int persistent_occupancy(ditr_ctx* c, int block, size_t lds, int* per_cu);
 int persistent_static_lds_impl(int block, size_t* bytes);
 int persistent_configure(ditr_ctx* c, size_t cu_lds, size_t block_lds);
+
+int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, double* d_h, float* d_f,
+                double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total);

@@ -186,6 +186,7 @@ struct PartArgs {
   int lds_edges;   // local-target capacity (a larger partition reads its targets from memory)
   float alpha;
   float d;
+  double dd;  // damping in FP64 for the published shares
 };
 
 // lane owning edge slot e: first lane whose inclusive prefix exceeds e
@@ -431,7 +432,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
           a.H[lo + i] = hv[u] + dh;
           const int od = odeg[i];
           if (od > 0) {
-            so = (float)((double)d * dh / (double)od);
+            so = (float)(a.dd * dh / (double)od);
             // in flight to the outside targets of i
             resid += fabs((double)so) * (double)(od - (lptr[i + 1] - lptr[i]));
           }
@@ -742,6 +743,7 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   a.lds_nodes = std::max(1, g->max_part);
   a.alpha = (float)alpha;
   a.d = (float)g->d;
+  a.dd = g->d;
   if (part_lds_bytes(a.lds_nodes, 0) > c->part_lds_dyn)
     return set_error(DITR_EINVAL, "partition of %d nodes needs %zu B of LDS (limit %zu)", a.lds_nodes,
                      part_lds_bytes(a.lds_nodes, 0), c->part_lds_dyn);

@@ -93,6 +93,8 @@ _SIGNATURES = {
     "ditr_residual": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)], _i32),
     "ditr_solve": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
                     ctypes.POINTER(Stats)], _i32),
+    "ditr_solve_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
+                            _vp, ctypes.POINTER(Stats)], _i32),
 }
 
 
@@ -249,3 +251,25 @@ def solve(ctx: Context, g: Graph, b, h, f, warm: bool = False, rel_tol: float = 
                           rel_tol, ctypes.byref(o), ctypes.byref(st))
     check(rc, allow)
     return st
+
+
+def solve_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, opts: Opts = None,
+                  allow=(OK, NOT_CONVERGED, ABORTED)):
+    """ditr_solve_batched: node-major [n, R] right-hand sides; returns (total, per_rhs)."""
+    torch = ctx.torch
+    if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
+        raise TypeError("b, h must be float64 and f float32")
+    if b.dim() != 2 or b.shape[0] != g.n or h.shape != b.shape or f.shape != b.shape:
+        raise ValueError("b, h, f must be [n, R] with the same shape")
+    for t in (b, h, f):
+        if not (t.is_contiguous() and t.is_cuda):
+            raise ValueError("b, h, f must be contiguous device tensors")
+    R = b.shape[1]
+    per = (Stats * R)()
+    tot = Stats()
+    o = opts if opts is not None else opts_default()
+    rc = lib().ditr_solve_batched(ctx.handle, g.handle, R, _ptr(b), _ptr(h), _ptr(f), rel_tol,
+                                  ctypes.byref(o), ctypes.cast(per, ctypes.c_void_p),
+                                  ctypes.byref(tot))
+    check(rc, allow)
+    return tot, list(per)

@@ -1,0 +1,114 @@
+"""GPU parity of the batched personalized solve (many right-hand sides).
+
+Each right-hand side B_r is a personalization vector (Section 2.2: V in
+X = d Q X + (1-d) V) with mass 0.15 on a seed set. Every column of the
+batched H must satisfy the same bound-based parity as a plain solve against an
+independent oracle run with B_r alone, and the returned F must be the exact
+residual of its column.
+"""
+import numpy as np
+import pytest
+
+import ditgen
+import oracle
+from conftest import D, sparse_p
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1202_6168_amd import ditr  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ditr.Context(0)
+    yield c
+    c.close()
+
+
+def run_batched(ctx, cp, ri, B, tol, **opt):
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+    bt = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    ht = torch.empty_like(bt)
+    ft = torch.empty(B.shape, dtype=torch.float32, device=dev)
+    tot, per = ditr.solve_batched(ctx, g, bt, ht, ft, rel_tol=tol, opts=ditr.opts_default(**opt))
+    torch.cuda.synchronize()
+    out = ht.cpu().numpy(), ft.cpu().numpy().astype(np.float64), tot, per
+    g.close()
+    return out
+
+
+def check_columns(cp, ri, B, H, F, per, tol, cols):
+    P = sparse_p(cp, ri)
+    for r in cols:
+        b = B[:, r]
+        ref = oracle.solve(cp, ri, b, rel_tol=1e-12)
+        assert per[r].status == ditr.OK
+        assert per[r].resid_l1 <= tol * np.abs(b).sum() * (1 + 1e-12)
+        err = np.abs(H[:, r] - ref.h).sum()
+        assert err <= (per[r].resid_l1 + ref.resid_l1) / (1 - D) * (1 + 1e-6), (r, err)
+        assert err <= 1e-6 * ref.h.sum()
+        ident = b + P @ H[:, r] - H[:, r]
+        assert np.abs(F[:, r] - ident).sum() <= 1e-7 * np.abs(ident).sum() + 1e-14 * np.abs(H[:, r]).sum()
+
+
+@pytest.mark.parametrize("R", [4, 16, 64])
+def test_batched_parity_small(ctx, R):
+    spec = ditgen.GraphSpec(n=20_000, block=1000, seed=5)
+    cp, ri = ditgen.generate(spec)
+    sets = ditgen.ppr_seed_sets(spec.n, R, seed=42)
+    B = ditgen.ppr_rhs_dense(spec.n, sets)
+    H, F, tot, per = run_batched(ctx, cp, ri, B, 1e-8)
+    assert tot.status == ditr.OK
+    check_columns(cp, ri, B, H, F, per, 1e-8, range(R) if R <= 16 else [0, 1, R // 2, R - 1])
+
+
+def test_batched_uneven_and_uniform_columns(ctx):
+    """Seed sets of very different sizes and a uniform column in one batch."""
+    spec = ditgen.GraphSpec(n=30_000, block=1000, seed=8)
+    cp, ri = ditgen.generate(spec)
+    sets = [np.array([0]), np.arange(1000), np.array([spec.n - 1]), np.arange(0, spec.n, 7)]
+    B = ditgen.ppr_rhs_dense(spec.n, sets)
+    B = np.concatenate([B, ditgen.uniform_b(spec.n)[:, None], np.zeros((spec.n, 3))], axis=1)
+    B[5, 6] = 0.3  # one seed, other mass
+    H, F, tot, per = run_batched(ctx, cp, ri, B, 1e-9)
+    check_columns(cp, ri, B, H, F, per, 1e-9, [0, 1, 2, 3, 4, 6])
+    # an all-zero right-hand side stays at H = 0 with nothing diffused
+    assert np.all(H[:, 5] == 0) and np.all(F[:, 5] == 0) and per[5].edges == 0
+
+
+def test_batched_matches_plain_solves(ctx):
+    spec = ditgen.GraphSpec(n=50_000, block=1000, seed=9)
+    cp, ri = ditgen.generate(spec)
+    sets = ditgen.ppr_seed_sets(spec.n, 8, seed=7)
+    B = ditgen.ppr_rhs_dense(spec.n, sets)
+    H, F, tot, per = run_batched(ctx, cp, ri, B, 1e-9)
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+    for r in range(8):
+        bt = torch.from_numpy(np.ascontiguousarray(B[:, r])).to(dev)
+        ht = torch.empty(spec.n, dtype=torch.float64, device=dev)
+        ft = torch.empty(spec.n, dtype=torch.float32, device=dev)
+        st = ditr.solve(ctx, g, bt, ht, ft, rel_tol=1e-9, allow=(ditr.OK,))
+        h = ht.cpu().numpy()
+        assert np.abs(h - H[:, r]).sum() <= (st.resid_l1 + per[r].resid_l1) / (1 - D) * (1 + 1e-6)
+    g.close()
+
+
+def test_batched_rejects_bad_shapes(ctx):
+    dev = torch.device("cuda", 0)
+    cp = torch.tensor([0, 1, 1], dtype=torch.int32, device=dev)
+    ri = torch.tensor([1], dtype=torch.int32, device=dev)
+    g = ditr.Graph(ctx, cp, ri)
+    b = torch.zeros((2, 6), dtype=torch.float64, device=dev)
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.solve_batched(ctx, g, b, torch.empty_like(b), torch.empty((2, 6), dtype=torch.float32, device=dev))
+    assert e.value.status == ditr.EINVAL
+    b = torch.full((2, 4), float("nan"), dtype=torch.float64, device=dev)
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.solve_batched(ctx, g, b, torch.empty_like(b), torch.empty((2, 4), dtype=torch.float32, device=dev))
+    assert e.value.status == ditr.ENONFINITE
+    g.close()
