@@ -41,6 +41,7 @@ typedef enum {
   DITR_OK = 0,
   DITR_NOT_CONVERGED = 1, /* budget hit; H and F are valid (F = B + P H - H holds) */
   DITR_ABORTED = 2,       /* ditr_abort() was called; H and F are valid */
+  DITR_NOT_FOUND = 3,     /* no tuning cache entry under the key */
   DITR_EINVAL = -1,       /* bad argument (null pointer, size, damping outside (0,1), ...) */
   DITR_EGRAPH = -2,       /* CSC is malformed (col_ptr not monotone, row out of range, ...) */
   DITR_ENOMEM = -3,       /* device or pinned host allocation failed */
@@ -174,6 +175,52 @@ int ditr_solve(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, double* d_
 int ditr_solve_batched(ditr_ctx* ctx, const ditr_graph* g, int nrhs, const double* d_b,
                        double* d_h, float* d_f, double rel_tol, const ditr_opts* opts,
                        ditr_stats* per_rhs, ditr_stats* total);
+
+/* ---- autotuner (step: partition size and threshold schedule) ----------- */
+typedef struct {
+  uint64_t key;            /* fingerprint of (CSC, damping, B, rel_tol, device) */
+  int32_t from_cache;      /* 1: options read from the cache, nothing timed */
+  int32_t candidates;      /* option sets timed */
+  double default_seconds;  /* time to tolerance with ditr_opts_default (re-timed at the end) */
+  double best_seconds;     /* time to tolerance with the returned options (same re-timing) */
+  int64_t default_edges;   /* diffused edges of those two solves */
+  int64_t best_edges;
+  double seconds;          /* host wall time of the tuning call */
+} ditr_tune_info;
+
+/* Pick the options of the plain solve that reach rel_tol ||B||_1 fastest on
+ * this problem: partition type and nodes per partition (Section 2.3), the
+ * threshold divisor alpha in [1.2, 2] (Section 2.4), local sweeps per launch
+ * and the first exact-refresh point, by coordinate descent over wall time to
+ * tolerance (effort 0: partition size and alpha; 1: also local sweeps and the
+ * refresh point; 2: a second pass). The returned options are never slower than
+ * the defaults at the final re-timing, else they are the defaults.
+ * The CSC arrays follow ditr_graph_create; d_b FP64 [n] is the right-hand side
+ * to tune for; d_h FP64 [n] and d_f FP32 [n] are work buffers (overwritten).
+ * If cache_path != NULL the result is looked up there first, under the key
+ * ditr_tune_key computes, and stored there afterwards (a JSON file rewritten
+ * through a temporary file and a rename; concurrent writers may lose entries
+ * but never corrupt it; an unreadable file counts as empty). Builds and
+ * destroys its own graphs. Synchronizes. */
+int ditr_tune(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+              const int32_t* d_row_idx, double damping, const double* d_b, double* d_h, float* d_f,
+              double rel_tol, int effort, const char* cache_path, ditr_opts* out,
+              ditr_tune_info* info);
+/* The cache key of a problem: a position-aware hash of col_ptr, row_idx and B
+ * computed on the device, combined with n, nnz, damping, rel_tol and the
+ * device's architecture name and CU count. Synchronizes. */
+int ditr_tune_key(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+                  const int32_t* d_row_idx, double damping, const double* d_b, double rel_tol,
+                  uint64_t* key);
+/* Host-only access to a tuning cache file. get: copies the tuned fields
+ * (alpha, refresh_at, part_type, part_nodes, sweeps_per_claim) of the entry
+ * under `key` into *out and leaves the others; DITR_NOT_FOUND if the file is
+ * missing, not a cache, or has no such entry. put: adds or replaces that
+ * entry; DITR_EINVAL for options out of range or a file that cannot be
+ * written. */
+int ditr_tune_cache_get(const char* path, uint64_t key, ditr_opts* out);
+int ditr_tune_cache_put(const char* path, uint64_t key, const ditr_opts* o, double seconds,
+                        double default_seconds);
 
 #ifdef __cplusplus
 }

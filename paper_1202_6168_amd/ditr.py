@@ -15,13 +15,13 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libditr.so")
 
-OK, NOT_CONVERGED, ABORTED = 0, 1, 2
+OK, NOT_CONVERGED, ABORTED, NOT_FOUND = 0, 1, 2, 3
 EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
 PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
 
-_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "ABORTED", -1: "EINVAL", -2: "EGRAPH",
+_STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "ABORTED", 3: "NOT_FOUND", -1: "EINVAL", -2: "EGRAPH",
                  -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE"}
 
 
@@ -74,6 +74,22 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [
+        ("key", ctypes.c_uint64),
+        ("from_cache", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("default_seconds", ctypes.c_double),
+        ("best_seconds", ctypes.c_double),
+        ("default_edges", ctypes.c_int64),
+        ("best_edges", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -95,6 +111,13 @@ _SIGNATURES = {
                     ctypes.POINTER(Stats)], _i32),
     "ditr_solve_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                             _vp, ctypes.POINTER(Stats)], _i32),
+    "ditr_tune": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _dbl, _i32, ctypes.c_char_p,
+                   ctypes.POINTER(Opts), ctypes.POINTER(TuneInfo)], _i32),
+    "ditr_tune_key": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _dbl,
+                       ctypes.POINTER(ctypes.c_uint64)], _i32),
+    "ditr_tune_cache_get": ([ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts)], _i32),
+    "ditr_tune_cache_put": ([ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts), _dbl, _dbl],
+                            _i32),
 }
 
 
@@ -273,3 +296,58 @@ def solve_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, opts: 
                                   ctypes.byref(tot))
     check(rc, allow)
     return tot, list(per)
+
+
+def _check_problem(ctx, col_ptr, row_idx, b, h, f):
+    torch = ctx.torch
+    if col_ptr.dtype != torch.int32 or row_idx.dtype != torch.int32:
+        raise TypeError("CSC arrays must be int32")
+    n = col_ptr.numel() - 1
+    if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
+        raise TypeError("b, h must be float64 and f float32")
+    for t in (col_ptr, row_idx, b, h, f):
+        if not (t.is_contiguous() and t.is_cuda):
+            raise ValueError("arrays must be contiguous device tensors")
+    for t in (b, h, f):
+        if t.numel() != n:
+            raise ValueError("b, h, f must have length n")
+    return n, row_idx.numel()
+
+
+def tune_key(ctx: Context, col_ptr, row_idx, b, rel_tol: float, damping: float = 0.85) -> int:
+    """ditr_tune_key: cache key of (CSC, damping, B, rel_tol, device)."""
+    n, nnz = col_ptr.numel() - 1, row_idx.numel()
+    k = ctypes.c_uint64()
+    check(lib().ditr_tune_key(ctx.handle, n, nnz, _ptr(col_ptr), _ptr(row_idx) if nnz else None,
+                              damping, _ptr(b), rel_tol, ctypes.byref(k)))
+    return k.value
+
+
+def tune(ctx: Context, col_ptr, row_idx, b, h, f, rel_tol: float = 1e-9, effort: int = 1,
+         cache_path: str = None, damping: float = 0.85):
+    """ditr_tune: options of the fastest plain solve of this problem; returns (opts, info).
+    h and f are work buffers (overwritten)."""
+    n, nnz = _check_problem(ctx, col_ptr, row_idx, b, h, f)
+    o, info = Opts(), TuneInfo()
+    check(lib().ditr_tune(ctx.handle, n, nnz, _ptr(col_ptr), _ptr(row_idx) if nnz else None,
+                          damping, _ptr(b), _ptr(h), _ptr(f), rel_tol, effort,
+                          cache_path.encode() if cache_path else None, ctypes.byref(o),
+                          ctypes.byref(info)))
+    return o, info
+
+
+def tune_cache_get(path: str, key: int, base: Opts = None):
+    """ditr_tune_cache_get: the cached options under `key` over `base`, or None."""
+    o = Opts()
+    if base is not None:
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(base), ctypes.sizeof(Opts))
+    else:
+        check(lib().ditr_opts_default(ctypes.byref(o)))
+    rc = check(lib().ditr_tune_cache_get(path.encode(), key, ctypes.byref(o)), (OK, NOT_FOUND))
+    return o if rc == OK else None
+
+
+def tune_cache_put(path: str, key: int, o: Opts, seconds: float = 0.0,
+                   default_seconds: float = 0.0):
+    """ditr_tune_cache_put: add or replace the entry under `key`."""
+    check(lib().ditr_tune_cache_put(path.encode(), key, ctypes.byref(o), seconds, default_seconds))
