@@ -5,7 +5,7 @@ benchmark's CPU-baseline leg may import this module. The GPU library never
 imports it and shares no code with it.
 
 What is computed. A two-layer message-passing network predicts, per node,
-y = log(N x_i) of the PageRank solution x of X = P X + B (Section 1, equation
+y = log(N x_i / ||B||_1) of the solution x of X = P X + B (Section 1, equation
 affine; P of Section 2.2: p_ji = d / #out_i on each out-link i -> j, dangling
 columns zero). Its one graph operator is P itself, applied to node features:
 (P Z)_j = sum over in-links i -> j of d / #out_i * Z_i. The prediction gives
@@ -20,12 +20,21 @@ Model (hidden width 64, all FP64 here):
               for state i // block (a fixed code of the node's id block)
     layer 1   h1 = relu(X W1s + (P X) W1n + b1)
     layer 2   h2 = relu(h1 W2s + (P h1) W2n + b2)
-    head      yhat = h2 w3 + b3
+    head      z = h2 w3 + b3,  yhat = log(softplus(z))
     loss      L = sum_i w_i (yhat_i - y_i)^2
-Training targets from a solved H (uniform B, ||B||_1 = 1 - d):
-y_i = log(N H_i (1 - d) / ||B||_1), w_i = H_i / sum H (the first-order weight
-of node i in the L1 error of the start, which is what the D-iteration has to
-diffuse). Optimizer: Adam (Kingma and Ba, 2015, Algorithm 1).
+The log link lets the network form y as the log of a positive combination of
+aggregates: the solution is the series B + P B + P^2 B + ... (Section 1), whose
+first terms two aggregation layers can carry linearly.
+Training targets from a solved H: y_i = log(N H_i / ||B||_1), w_i = H_i / sum H
+(the first-order weight of node i in the L1 error of the start, which is the
+fluid the D-iteration then has to diffuse). Optimizer: Adam (Kingma and Ba,
+2015, Algorithm 1).
+
+Warm start: xhat = exp(yhat) ||B||_1 / N, H_0 = c xhat with c taken from
+{0} and {0.50, 0.55, ..., 1.50} to minimize ||B + c (P - I) xhat||_1, the L1
+fluid of the start (Section 2: the error bound and the remaining work are in
+that norm); c = 0 is the cold start H_0 = 0, F_0 = B, so the start never holds
+more fluid than B.
 
 Flat parameter order (the C-ABI uses the same): W1s [8][64], W1n [8][64],
 b1 [64], W2s [64][64], W2n [64][64], b2 [64], w3 [64], b3 [1]; matrices are
@@ -108,8 +117,10 @@ def forward(params, X, P):
     A1 = P @ h1
     z2 = h1 @ params["W2s"] + A1 @ params["W2n"] + params["b2"]
     h2 = np.maximum(z2, 0.0)
-    yhat = h2 @ params["w3"] + params["b3"][0]
-    return dict(AX=AX, z1=z1, h1=h1, A1=A1, z2=z2, h2=h2, yhat=yhat)
+    z = h2 @ params["w3"] + params["b3"][0]
+    sp = np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z)))  # softplus, overflow-free
+    yhat = np.log(sp)
+    return dict(AX=AX, z1=z1, h1=h1, A1=A1, z2=z2, h2=h2, z=z, sp=sp, yhat=yhat)
 
 
 def loss(params, X, P, y, w):
@@ -123,8 +134,9 @@ def loss_and_grad(params, X, P, y, w):
     r = fw["yhat"] - y
     L = float(np.sum(w * r * r))
     dy = 2.0 * w * r                                   # dL/dyhat
-    g = {"w3": fw["h2"].T @ dy, "b3": np.array([dy.sum()])}
-    gz2 = np.outer(dy, params["w3"]) * (fw["z2"] > 0)  # through relu of layer 2
+    dz = dy / fw["sp"] / (1.0 + np.exp(-fw["z"]))      # d log softplus(z)/dz = sigmoid(z)/softplus(z)
+    g = {"w3": fw["h2"].T @ dz, "b3": np.array([dz.sum()])}
+    gz2 = np.outer(dz, params["w3"]) * (fw["z2"] > 0)  # through relu of layer 2
     g["W2s"] = fw["h1"].T @ gz2
     g["W2n"] = fw["A1"].T @ gz2
     g["b2"] = gz2.sum(axis=0)
@@ -137,14 +149,17 @@ def loss_and_grad(params, X, P, y, w):
     return L, g
 
 
-def targets(h, b_l1, mass=0.15):
-    """Training targets from a solved history H: y = log(N H (1-d) / ||B||_1),
+def targets(h, b_l1):
+    """Training targets from a solved history H: y = log(N H / ||B||_1),
     w = H / sum H."""
     h = np.asarray(h, np.float64)
     n = h.size
-    y = np.log(n * h * (mass / b_l1))
+    y = np.log(n * h / b_l1)
     w = h / h.sum()
     return y, w
+
+
+SCALES = np.concatenate([[0.0], 0.5 + 0.05 * np.arange(21)])
 
 
 def adam(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -157,20 +172,17 @@ def adam(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def warm_start(yhat, P, b, mass=0.15):
-    """H_0 from a prediction: xhat = exp(yhat) / N * ||B||_1 / (1-d), scaled by
-    the c that minimizes ||B + c (P - I) xhat||_2 (closed form
-    c = -<B, r> / <r, r> with r = P xhat - xhat); H_0 = 0 if the exact fluid of
-    that start, F_0 = B + P H_0 - H_0, is larger in L1 than B (a cold start).
-    Returns (H_0, F_0, c, fell_back)."""
+def warm_start(yhat, P, b):
+    """H_0 from a prediction: xhat = exp(yhat) ||B||_1 / N, H_0 = c xhat with c
+    the first of SCALES that minimizes ||B + c (P - I) xhat||_1 (c = 0: cold
+    start). Returns (H_0, F_0 = B + P H_0 - H_0, c, fell_back = (c == 0))."""
     n = b.size
     b1 = np.abs(b).sum()
-    xhat = np.exp(yhat) / n * (b1 / mass)
+    xhat = np.exp(yhat) * (b1 / n)
     r = P @ xhat - xhat
-    rr = float(r @ r)
-    c = -float(b @ r) / rr if rr > 0 else 1.0
-    h0 = c * xhat
-    f0 = b + P @ h0 - h0
-    if np.abs(f0).sum() > b1:
+    l1 = [np.abs(b + c * r).sum() for c in SCALES]
+    c = float(SCALES[int(np.argmin(l1))])
+    if c == 0.0:
         return np.zeros(n), b.copy(), c, True
-    return h0, f0, c, False
+    h0 = c * xhat
+    return h0, b + P @ h0 - h0, c, False

@@ -8,8 +8,9 @@
 - every gradient component against central finite differences (FP64);
 - planted mistakes in the backward pass, each caught by that check;
 - Adam against torch.optim.Adam;
-- the warm start: the scale minimizes ||B + c (P - I) xhat||_2, an exact
-  prediction leaves (almost) no fluid, a bad one falls back to H_0 = 0.
+- the warm start: the scale minimizes ||B + c (P - I) xhat||_1 over its grid,
+  an exact prediction leaves (almost) no fluid, a bad one falls back to
+  H_0 = 0.
 """
 import inspect
 import textwrap
@@ -133,6 +134,8 @@ MUTANTS = {
     "dropped_bias_gradient": ("g[\"b2\"] = gz2.sum(axis=0)", "g[\"b2\"] = 0 * gz2.sum(axis=0)"),
     "missing_factor_two": ("dy = 2.0 * w * r", "dy = w * r"),
     "transposed_layer2_weights": ("gz2 @ params[\"W2s\"].T", "gz2 @ params[\"W2s\"]"),
+    "link_derivative_without_sigmoid": ("dz = dy / fw[\"sp\"] / (1.0 + np.exp(-fw[\"z\"]))",
+                                        "dz = dy / fw[\"sp\"]"),
 }
 
 
@@ -177,10 +180,20 @@ def test_flat_layout():
 def test_targets_invert_to_h():
     h = np.array([0.2, 0.5, 1.0, 3.0]) * 0.15 / 4
     y, w = gnn.targets(h, b_l1=0.15)
-    assert np.allclose(np.exp(y) / 4, h, rtol=1e-15) and np.isclose(w.sum(), 1.0)
+    assert np.allclose(np.exp(y) * 0.15 / 4, h, rtol=1e-15) and np.isclose(w.sum(), 1.0)
     # scaling B scales H: the target of a scaled solve is unchanged
     y2, _ = gnn.targets(3 * h, b_l1=0.45)
     assert np.allclose(y, y2, rtol=0, atol=1e-15)
+
+
+def test_head_link_values():
+    # yhat = log(softplus(z)): a large z gives log z, a very negative z gives z
+    p = gnn.unflatten(np.zeros(gnn.N_PARAMS))
+    X = np.zeros((3, 8))
+    P = gnn.p_matrix(np.array([0, 0, 0, 0]), np.array([], dtype=np.int32))
+    for b3, want in ((0.0, np.log(np.log(2.0))), (50.0, np.log(50.0)), (-40.0, -40.0)):
+        p["b3"][0] = b3
+        assert np.allclose(gnn.forward(p, X, P)["yhat"], want, rtol=1e-12, atol=1e-12)
 
 
 def test_warm_start_scale_and_fallback():
@@ -192,24 +205,23 @@ def test_warm_start_scale_and_fallback():
     # exact prediction: c = 1 and no fluid left beyond the oracle's own residual
     y, _ = gnn.targets(ref.h, 0.15)
     h0, f0, c, fb = gnn.warm_start(y, P, b)
-    assert not fb and abs(c - 1) < 1e-9 and np.abs(f0).sum() <= 1e-9 * 0.15
-    # a prediction off by a constant factor is rescaled back
-    h0, f0, c, fb = gnn.warm_start(y + np.log(3.0), P, b)
-    assert not fb and abs(c - 1 / 3) < 1e-9
-    # the scale minimizes the 2-norm of the start's fluid
+    assert not fb and c == 1.0 and np.abs(f0).sum() <= 1e-9 * 0.15
+    # a prediction 25% too large is scaled back by the grid point 0.8
+    h0, f0, c, fb = gnn.warm_start(y + np.log(1.25), P, b)
+    assert not fb and c == 0.8 and np.abs(f0).sum() <= 1e-9 * 0.15
+    # the chosen scale minimizes the L1 fluid over the grid, never above ||B||_1
     rng = np.random.default_rng(2)
     y_noisy = y + rng.normal(0, 0.3, n)
     h0, f0, c, fb = gnn.warm_start(y_noisy, P, b)
-    xhat = np.exp(y_noisy) / n
+    xhat = np.exp(y_noisy) * 0.15 / n
     r = P @ xhat - xhat
-    for dc in (1e-3, -1e-3):
-        assert np.linalg.norm(b + c * r) <= np.linalg.norm(b + (c + dc) * r)
-    if not fb:
-        assert np.allclose(f0, b + P @ h0 - h0, rtol=0, atol=1e-15)
+    best = min(np.abs(b + s * r).sum() for s in gnn.SCALES)
+    assert np.isclose(np.abs(f0).sum(), best, rtol=1e-12)
     assert np.abs(f0).sum() <= np.abs(b).sum()
+    assert np.allclose(f0, b + P @ h0 - h0, rtol=0, atol=1e-15)
     # a personalized B (one seed node) with an unrelated prediction: every
     # scale leaves more L1 fluid than B itself, so the start falls back to cold
     b1 = np.zeros(n)
     b1[7] = 0.15
     h0, f0, c, fb = gnn.warm_start(rng.normal(0, 3, n), P, b1)
-    assert fb and np.all(h0 == 0) and np.array_equal(f0, b1)
+    assert fb and c == 0.0 and np.all(h0 == 0) and np.array_equal(f0, b1)
