@@ -24,6 +24,8 @@
  *   - Every function returns a ditr_status. No exception or abort crosses
  *     the ABI; ditr_last_error() gives a message for the calling thread.
  *   - A context is used from one host thread at a time (ditr_abort excepted).
+ *   - Graphs, tuning calls and networks use their context while they run; they
+ *     may be destroyed after it (their destroy waits for the device).
  */
 #ifndef DITR_H
 #define DITR_H
@@ -221,6 +223,78 @@ int ditr_tune_key(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_pt
 int ditr_tune_cache_get(const char* path, uint64_t key, ditr_opts* out);
 int ditr_tune_cache_put(const char* path, uint64_t key, const ditr_opts* o, double seconds,
                         double default_seconds);
+
+/* ---- learned warm start (step: network, training, predicted H_0) ------- */
+/* A two-layer message-passing network over P predicts y_i = log(N x_i / ||B||_1)
+ * of the solution x of X = P X + B (Section 1) for uniform B; its prediction gives a
+ * start H_0 whose exact fluid F_0 = B + P H_0 - H_0 (identity of equations
+ * defF and defH) is all the D-iteration then diffuses (ditr_solve, warm = 1).
+ *   features X_i = [log1p #in_i, log1p #out_i, [#out_i = 0], 1,
+ *                   u_k = ((s >> 16k) & 0xffff) / 32768 - 1, k = 0..3],
+ *                  s = SplitMix64 output for state i / block
+ *   h1 = relu(X W1s + (P X) W1n + b1),  h2 = relu(h1 W2s + (P h1) W2n + b2)
+ *   z = h2 w3 + b3, yhat = log(softplus(z));  training loss sum_i w_i (yhat_i - y_i)^2
+ * BF16 weights and activations (round to nearest even), FP32 accumulation,
+ * FP32 master weights, FP32 gradients, Adam (beta 0.9, 0.999, eps 1e-8).
+ * Parameters are exchanged as one FP32 vector in this order, matrices
+ * [input][output] row-major: W1s [8][64], W1n [8][64], b1 [64], W2s [64][64],
+ * W2n [64][64], b2 [64], w3 [64], b3 [1]. The network holds device buffers
+ * for the largest graph it has seen (about 900 bytes per node when training).
+ * A network is used with graphs of the context it was created on. */
+typedef struct ditr_gnn ditr_gnn;
+#define DITR_GNN_PARAMS 9409
+enum { DITR_GNN_ACT_X = 0,   /* features, BF16 [n][16] (8 used, 8 zero) */
+       DITR_GNN_ACT_PX = 1,  /* P X, BF16 [n][16] */
+       DITR_GNN_ACT_H1 = 2,  /* BF16 [n][64] */
+       DITR_GNN_ACT_PH1 = 3, /* P h1, BF16 [n][64] */
+       DITR_GNN_ACT_H2 = 4   /* BF16 [n][64] */ };
+
+typedef struct {
+  double b_l1;      /* ||B||_1 */
+  double scale_c;   /* scale applied to xhat (0: cold start) */
+  double f0_l1;     /* exact ||F_0||_1 of the returned H_0 (FP64) */
+  int32_t fell_back;/* 1: H_0 = 0 (no scaled start leaves less L1 fluid than B) */
+  int32_t pad;
+  double seconds;   /* host wall time of the call */
+} ditr_gnn_start;
+
+/* hidden must be 64; block is the id-block size of the code features; seed
+ * draws He-normal initial weights (SplitMix64, Box-Muller), zero biases, and a
+ * head that starts near z = 1 (w3 scaled by 0.1, b3 = 1). */
+int ditr_gnn_create(ditr_ctx* ctx, ditr_gnn** out, int hidden, int block, uint64_t seed);
+int ditr_gnn_destroy(ditr_gnn* net);
+/* h_theta: host FP32 [DITR_GNN_PARAMS]. set also clears the Adam state.
+ * Synchronize. DITR_ENONFINITE for a NaN or Inf parameter. */
+int ditr_gnn_get_params(ditr_gnn* net, float* h_theta);
+int ditr_gnn_set_params(ditr_gnn* net, const float* h_theta);
+/* yhat of every node of g into d_yhat (device FP32 [n], may be NULL). */
+int ditr_gnn_forward(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, float* d_yhat);
+/* Copy an activation of the last forward pass (DITR_GNN_ACT_*) for n nodes. */
+int ditr_gnn_activation(ditr_ctx* ctx, const ditr_gnn* net, int which, int64_t n, uint16_t* d_out);
+/* Training targets from a solved H (device FP64 [n]) of a right-hand side with
+ * ||B||_1 = b_l1: y_i = log(N H_i / b_l1) and w_i = H_i / sum H (zero where
+ * H_i <= 0). d_y, d_w: device FP32 [n].
+ * Synchronizes. */
+int ditr_gnn_targets(ditr_ctx* ctx, const ditr_graph* g, const double* d_h, double b_l1, float* d_y,
+                     float* d_w);
+/* Loss and its gradient at the current weights (forward + backward on g).
+ * d_grad: device FP32 [DITR_GNN_PARAMS] (may be NULL); h_loss (may be NULL,
+ * synchronizes). */
+int ditr_gnn_grad(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, const float* d_y,
+                  const float* d_w, float* d_grad, double* h_loss);
+/* One Adam step with learning rate lr on the gradient of g's loss; h_loss gets
+ * the loss before the step (may be NULL, synchronizes). */
+int ditr_gnn_train_step(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, const float* d_y,
+                        const float* d_w, double lr, double* h_loss);
+/* Warm start for right-hand side d_b (device FP64 [n]): xhat = exp(yhat)
+ * ||B||_1 / N, H_0 = c xhat into d_h0 (device FP64 [n]) with c the first of
+ * {0, 0.50, 0.55, ..., 1.50} that minimizes the L1 fluid ||B + c (P - I) xhat||_1
+ * of the start (evaluated from the FP32 residual); d_f0 (device FP32 [n]) gets
+ * the exact fluid B + P H_0 - H_0. c = 0 is the cold start H_0 = 0, F_0 = B
+ * (info->fell_back = 1), so the start never holds more fluid than B. Then
+ * ditr_solve(..., warm = 1, ...) diffuses from H_0. Synchronizes. */
+int ditr_gnn_predict_h0(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, const double* d_b,
+                        double* d_h0, float* d_f0, ditr_gnn_start* info);
 
 #ifdef __cplusplus
 }

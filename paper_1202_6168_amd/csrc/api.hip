@@ -158,8 +158,10 @@ int ditr_partition(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr
 
 int ditr_graph_destroy(ditr_graph* g) {
   if (!g) return DITR_OK;
-  (void)hipSetDevice(g->ctx->device);
-  (void)hipStreamSynchronize(g->ctx->stream);
+  // the graph may outlive its context: use its own device id, and wait for the
+  // whole device rather than the context's stream
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
   (void)hipFree(g->row_ptr);
   (void)hipFree(g->csr_col);
   (void)hipFree(g->heavy_rows);
@@ -242,6 +244,7 @@ int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
   ditr_graph* g = new (std::nothrow) ditr_graph();
   if (!g) return set_error(DITR_ENOMEM, "host allocation failed");
   g->ctx = c;
+  g->device = c->device;
   g->n = n;
   g->nnz = nnz;
   g->d = damping;
@@ -382,7 +385,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   }
   st.b_l1 = b1;
   const double target = rel_tol * b1;
-  bool refreshed = warm != 0;
+  // a warm start's FP32 fluid drifts like a cold one's: the same first stage applies
+  bool refreshed = false;
 
   // persistent plan: static binding when every partition gets its own resident workgroup
   PersistentCfg cfg;

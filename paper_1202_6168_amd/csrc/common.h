@@ -69,6 +69,7 @@ struct PartPlan {
 
 struct ditr_graph {
   ditr_ctx* ctx = nullptr;
+  int device = 0;                    // device of the context it was created on
   int64_t n = 0, nnz = 0;
   double d = 0.85;
   const int32_t* col_ptr = nullptr;  // borrowed

@@ -1,0 +1,1051 @@
+// Learned warm start: a two-layer message-passing network over the PageRank
+// operator P (Section 2.2: p_ji = d / #out_i on each out-link i -> j) that
+// predicts y = log(N x_i) of the solution of X = P X + B (Section 1), trained
+// on solutions of the plain solver. Its prediction gives H_0; the exact fluid
+// F_0 = B + P H_0 - H_0 (identity of equations defF and defH) is then all the
+// D-iteration has to diffuse.
+//
+//   features X_i = [log1p #in, log1p #out, dangling, 1, 4 codes of i / block]
+//   h1 = relu(X W1s + (P X) W1n + b1),  h2 = relu(h1 W2s + (P h1) W2n + b2)
+//   z = h2 w3 + b3,  yhat = log(softplus(z)),  loss = sum_i w_i (yhat_i - y_i)^2
+//
+// Precision: BF16 activations and weights (round to nearest even), FP32
+// accumulation in the MFMA tiles and aggregates, FP32 master weights and Adam
+// state, FP32 gradients. Layouts in HBM: node-major rows, X/PX [n][16] (8
+// features, zero padded to one MFMA k-step), hidden [n][64].
+//
+// Kernels: sparse aggregation P Z pulled over the transpose (heavy rows split
+// in 2048-link chunks), its adjoint P^T G gathered over the CSC columns, and
+// the dense layers on 16x16x16 BF16 MFMA tiles (forward, input gradient and
+// weight gradient), one wave per 16-node tile.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kF0 = 16;   // padded feature width
+constexpr int kHid = 64;  // hidden width
+constexpr int kNP = DITR_GNN_PARAMS;
+// canonical offsets of the flat parameter vector
+constexpr int oW1s = 0, oW1n = 512, ob1 = 1024, oW2s = 1088, oW2n = 5184, ob2 = 9280,
+              ow3 = 9344, ob3 = 9408;
+constexpr int kSmall = 3 * kHid + 1;  // b1, b2, w3, b3 (BF16-rounded, as float)
+constexpr int kBwdBlocks = 256;       // blocks of the weight-gradient kernels
+constexpr int kHeadBlocks = 256;
+constexpr int kSumBlocks = 256;
+
+double wall_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float((h & 0xFFFFu) << 16); }
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+}
+__device__ __forceinline__ void unpack8(const uint4 v, float* f) {
+  f[0] = bf_lo(v.x); f[1] = bf_hi(v.x); f[2] = bf_lo(v.y); f[3] = bf_hi(v.y);
+  f[4] = bf_lo(v.z); f[5] = bf_hi(v.z); f[6] = bf_lo(v.w); f[7] = bf_hi(v.w);
+}
+__device__ __forceinline__ uint4 pack8(const float* f) {
+  return make_uint4(pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7]));
+}
+
+// log(softplus(z)) and its derivative sigmoid(z) / softplus(z). Below z = -20,
+// softplus(z) = e^z (1 - e^z / 2 + ...) is below FP32's reach of exp but its
+// log is z and the ratio 1 to within FP32 rounding.
+__device__ __forceinline__ float log_softplus(float z) {
+  return z < -20.f ? z : logf(fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))));
+}
+__device__ __forceinline__ float log_softplus_grad(float z) {
+  if (z < -20.f) return 1.f;
+  return 1.f / ((1.f + expf(-z)) * (fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)))));
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014): one output for a given state
+__device__ __forceinline__ uint64_t smix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int grid_of(int64_t work, int per_block, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (work + per_block - 1) / per_block));
+}
+
+// ---- features -----------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_features(int64_t n, const int32_t* __restrict__ col_ptr,
+                                                  const int32_t* __restrict__ row_ptr, int block,
+                                                  uint16_t* __restrict__ X) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int indeg = row_ptr[i + 1] - row_ptr[i];
+    const int outdeg = col_ptr[i + 1] - col_ptr[i];
+    const uint64_t s = smix((uint64_t)(i / block));
+    float f[16];
+    f[0] = log1pf((float)indeg);
+    f[1] = log1pf((float)outdeg);
+    f[2] = outdeg == 0 ? 1.f : 0.f;
+    f[3] = 1.f;
+    for (int k = 0; k < 4; ++k) f[4 + k] = (float)((s >> (16 * k)) & 0xFFFFu) / 32768.f - 1.f;
+    for (int k = 8; k < 16; ++k) f[k] = 0.f;
+    uint4* o = reinterpret_cast<uint4*>(X + i * kF0);
+    o[0] = pack8(f);
+    o[1] = pack8(f + 8);
+  }
+}
+
+// ---- aggregation (P Z)_j = sum_{i -> j} p_ji Z_i over the transpose -----------------
+// F/8 lanes per row, 8 features (16 bytes) per lane. Rows with more than
+// kHeavyRow in-links are left to the chunk kernels.
+template <int F>
+__global__ void __launch_bounds__(256) k_agg(int64_t n, const int32_t* __restrict__ row_ptr,
+                                             const int32_t* __restrict__ csr_col,
+                                             const float* __restrict__ pw,
+                                             const uint16_t* __restrict__ Z,
+                                             uint16_t* __restrict__ out) {
+  constexpr int LPR = F / 8;
+  const int sub = threadIdx.x % LPR;
+  const int64_t stride = (int64_t)gridDim.x * (256 / LPR);
+  for (int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR; j < n; j += stride) {
+    const int32_t e0 = row_ptr[j], e1 = row_ptr[j + 1];
+    if (e1 - e0 > kHeavyRow) continue;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t e = e0;
+    for (; e + 2 <= e1; e += 2) {
+      const int32_t i0 = csr_col[e], i1 = csr_col[e + 1];
+      const float p0 = pw[i0], p1 = pw[i1];
+      const uint4 v0 = *reinterpret_cast<const uint4*>(Z + (size_t)i0 * F + sub * 8);
+      const uint4 v1 = *reinterpret_cast<const uint4*>(Z + (size_t)i1 * F + sub * 8);
+      float a[8], b[8];
+      unpack8(v0, a);
+      unpack8(v1, b);
+      for (int k = 0; k < 8; ++k) acc[k] += p0 * a[k] + p1 * b[k];
+    }
+    if (e < e1) {
+      const int32_t i0 = csr_col[e];
+      const float p0 = pw[i0];
+      float a[8];
+      unpack8(*reinterpret_cast<const uint4*>(Z + (size_t)i0 * F + sub * 8), a);
+      for (int k = 0; k < 8; ++k) acc[k] += p0 * a[k];
+    }
+    *reinterpret_cast<uint4*>(out + (size_t)j * F + sub * 8) = pack8(acc);
+  }
+}
+
+// one workgroup per chunk of a heavy row's in-links: FP32 partial sum per chunk
+template <int F>
+__global__ void __launch_bounds__(256) k_agg_heavy(const int32_t* __restrict__ chunk_beg,
+                                                   const int32_t* __restrict__ chunk_end,
+                                                   const int32_t* __restrict__ csr_col,
+                                                   const float* __restrict__ pw,
+                                                   const uint16_t* __restrict__ Z,
+                                                   float* __restrict__ hpart) {
+  constexpr int LPR = F / 8, G = 256 / LPR;
+  __shared__ float red[G][F + 1];
+  const int c = blockIdx.x;
+  const int sub = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int32_t e = chunk_beg[c] + grp; e < chunk_end[c]; e += G) {
+    const int32_t i = csr_col[e];
+    const float p = pw[i];
+    float a[8];
+    unpack8(*reinterpret_cast<const uint4*>(Z + (size_t)i * F + sub * 8), a);
+    for (int k = 0; k < 8; ++k) acc[k] += p * a[k];
+  }
+  for (int k = 0; k < 8; ++k) red[grp][sub * 8 + k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < F) {
+    float s = 0.f;
+    for (int q = 0; q < G; ++q) s += red[q][threadIdx.x];
+    hpart[(size_t)c * F + threadIdx.x] = s;
+  }
+}
+
+// heavy rows: sum of their chunks (contiguous, ascending by heavy row)
+template <int F>
+__global__ void __launch_bounds__(256) k_agg_heavy_fin(int nh, const int32_t* __restrict__ heavy_rows,
+                                                       const int32_t* __restrict__ chunk_h,
+                                                       int n_chunks, const float* __restrict__ hpart,
+                                                       uint16_t* __restrict__ out) {
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < (int64_t)nh * F;
+       idx += (int64_t)gridDim.x * 256) {
+    const int h = (int)(idx / F), t = (int)(idx % F);
+    int lo = 0, hi = n_chunks;  // first chunk of row h
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (chunk_h[mid] < h) lo = mid + 1; else hi = mid;
+    }
+    float s = 0.f;
+    for (int c = lo; c < n_chunks && chunk_h[c] == h; ++c) s += hpart[(size_t)c * F + t];
+    out[(size_t)heavy_rows[h] * F + t] = f2bf(s);
+  }
+}
+
+// ---- dense layer: out = relu([Z | P Z] W + b) on MFMA tiles ---------------------
+// A wave computes 16 nodes x 64 outputs: (2 FIN / 16) k-steps x 4 output blocks
+// of v_mfma_f32_16x16x16_bf16. Operand layout (64 lanes, r = lane % 16,
+// q = lane / 16): A lane holds A[r][4q..4q+3], B lane holds B[4q..4q+3][r], the
+// result lane holds C[4q+i][r]. Wf is [64 out][2 FIN in] so a lane's B operand
+// is one 8-byte read. With HEAD the layer also writes z = out . w3 + b3 and
+// yhat = log(softplus(z)).
+template <int FIN, bool HEAD>
+__global__ void __launch_bounds__(256) k_dense(int64_t n, const uint16_t* __restrict__ Z,
+                                               const uint16_t* __restrict__ AZ,
+                                               const uint16_t* __restrict__ Wf,
+                                               const float* __restrict__ bias,
+                                               const float* __restrict__ w3, const float* __restrict__ b3,
+                                               uint16_t* __restrict__ out, float* __restrict__ zout,
+                                               float* __restrict__ yhat) {
+  constexpr int K = 2 * FIN;
+  __shared__ __attribute__((aligned(16))) uint16_t sW[kHid * K];
+  __shared__ __attribute__((aligned(16))) uint16_t sO[4][16 * kHid];
+  for (int t = threadIdx.x; t < kHid * K / 8; t += 256)
+    reinterpret_cast<uint4*>(sW)[t] = reinterpret_cast<const uint4*>(Wf)[t];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  float bia[4], wv[4];
+  for (int nb = 0; nb < 4; ++nb) {
+    bia[nb] = bias[nb * 16 + r];
+    wv[nb] = HEAD ? w3[nb * 16 + r] : 0.f;
+  }
+  const float bb3 = HEAD ? b3[0] : 0.f;
+  __syncthreads();
+  const int64_t groups = (n + 63) / 64;  // 4 tiles of 16 nodes per block step
+  for (int64_t tg = blockIdx.x; tg < groups; tg += gridDim.x) {
+    const int64_t tile = tg * 4 + wave;
+    const int64_t node = tile * 16 + r;
+    f32x4 acc[4];
+    for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < K / 16; ++ks) {
+      const int kb = ks * 16 + q * 4;
+      const uint16_t* src = kb < FIN ? Z : AZ;
+      const int col = kb < FIN ? kb : kb - FIN;
+      bf16x4 a = bf16x4{0, 0, 0, 0};
+      if (node < n) a = *reinterpret_cast<const bf16x4*>(src + node * FIN + col);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sW[(nb * 16 + r) * K + kb]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+      }
+    }
+    float ys[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint16_t h = f2bf(fmaxf(acc[nb][i] + bia[nb], 0.f));
+        sO[wave][(4 * q + i) * kHid + nb * 16 + r] = h;
+        if (HEAD) ys[i] += bf2f(h) * wv[nb];
+      }
+    if (HEAD) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v = ys[i];
+        for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+        const int64_t nd = tile * 16 + 4 * q + i;
+        if (r == 0 && nd < n) {
+          const float z = v + bb3;
+          zout[nd] = z;
+          yhat[nd] = log_softplus(z);
+        }
+      }
+    }
+    __syncthreads();
+    {  // 16 rows x 128 bytes per wave, 32 bytes per lane
+      const int row = lane >> 2, part = lane & 3;
+      const int64_t nd = tile * 16 + row;
+      if (nd < n) {
+        const uint4* s = reinterpret_cast<const uint4*>(&sO[wave][row * kHid + part * 16]);
+        uint4* d = reinterpret_cast<uint4*>(out + nd * kHid + part * 16);
+        d[0] = s[0];
+        d[1] = s[1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- head: loss, dL/dz and the gradient entering layer 2 -------------------------
+// dyhat/dz = sigmoid(z) / softplus(z). 8 lanes per node.
+// part[block] = [dL/dw3 (64), dL/db3, loss]
+__global__ void __launch_bounds__(256) k_head_bwd(int64_t n, const uint16_t* __restrict__ H2,
+                                                  const float* __restrict__ zin,
+                                                  const float* __restrict__ yhat,
+                                                  const float* __restrict__ y,
+                                                  const float* __restrict__ w,
+                                                  const float* __restrict__ w3,
+                                                  uint16_t* __restrict__ G2, float* __restrict__ part) {
+  __shared__ float red[32][kHid + 2];
+  const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
+  float wv[8];
+  for (int k = 0; k < 8; ++k) wv[k] = w3[sub * 8 + k];
+  float gw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  float gb = 0.f, ls = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * 32;
+  for (int64_t i = (int64_t)blockIdx.x * 32 + grp; i < n; i += stride) {
+    const float rr = yhat[i] - y[i];
+    const float dy = 2.f * w[i] * rr * log_softplus_grad(zin[i]);
+    if (sub == 0) {
+      gb += dy;
+      ls += w[i] * rr * rr;
+    }
+    float h[8], g[8];
+    unpack8(*reinterpret_cast<const uint4*>(H2 + i * kHid + sub * 8), h);
+    for (int k = 0; k < 8; ++k) {
+      g[k] = h[k] > 0.f ? dy * wv[k] : 0.f;
+      gw[k] += dy * h[k];
+    }
+    *reinterpret_cast<uint4*>(G2 + i * kHid + sub * 8) = pack8(g);
+  }
+  for (int k = 0; k < 8; ++k) red[grp][sub * 8 + k] = gw[k];
+  if (sub == 0) {
+    red[grp][kHid] = gb;
+    red[grp][kHid + 1] = ls;
+  }
+  __syncthreads();
+  if (threadIdx.x < kHid + 2) {
+    float s = 0.f;
+    for (int q = 0; q < 32; ++q) s += red[q][threadIdx.x];
+    part[(size_t)blockIdx.x * (kHid + 2) + threadIdx.x] = s;
+  }
+}
+
+// ---- input gradient of layer 2: U = G2 [W2s | W2n]^T, [n][128] FP32 -------------
+// Wb is W2 in its natural [128 in][64 out] layout: a lane's B operand
+// B[k = out][n = in] = Wb[in][out .. out+3] is one 8-byte read.
+__global__ void __launch_bounds__(256) k_bwd_data(int64_t n, const uint16_t* __restrict__ G,
+                                                  const uint16_t* __restrict__ Wb,
+                                                  float* __restrict__ U) {
+  constexpr int NI = 2 * kHid;
+  __shared__ __attribute__((aligned(16))) uint16_t sW[NI * kHid];
+  __shared__ __attribute__((aligned(16))) float sO[4][16 * NI];
+  for (int t = threadIdx.x; t < NI * kHid / 8; t += 256)
+    reinterpret_cast<uint4*>(sW)[t] = reinterpret_cast<const uint4*>(Wb)[t];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  __syncthreads();
+  const int64_t groups = (n + 63) / 64;
+  for (int64_t tg = blockIdx.x; tg < groups; tg += gridDim.x) {
+    const int64_t tile = tg * 4 + wave;
+    const int64_t node = tile * 16 + r;
+    f32x4 acc[8];
+    for (int nb = 0; nb < 8; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kHid / 16; ++ks) {
+      const int kb = ks * 16 + q * 4;
+      bf16x4 a = bf16x4{0, 0, 0, 0};
+      if (node < n) a = *reinterpret_cast<const bf16x4*>(G + node * kHid + kb);
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sW[(nb * 16 + r) * kHid + kb]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sO[wave][(4 * q + i) * NI + nb * 16 + r] = acc[nb][i];
+    __syncthreads();
+    {  // 16 rows x 512 bytes per wave, 128 bytes per lane
+      const int row = lane >> 2, part = lane & 3;
+      const int64_t nd = tile * 16 + row;
+      if (nd < n) {
+        const float4* s = reinterpret_cast<const float4*>(&sO[wave][row * NI + part * 32]);
+        float4* d = reinterpret_cast<float4*>(U + nd * NI + part * 32);
+        for (int k = 0; k < 8; ++k) d[k] = s[k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- adjoint aggregation for layer 1: G1 = relu'(h1) (U_self + p_i sum_{i -> j} U_nbr[j]) --
+// gathered over the CSC columns (out-links of i); 8 lanes per node.
+__global__ void __launch_bounds__(256) k_agg_t(int64_t n, const int32_t* __restrict__ col_ptr,
+                                               const int32_t* __restrict__ row_idx,
+                                               const float* __restrict__ pw,
+                                               const float* __restrict__ U,
+                                               const uint16_t* __restrict__ H1,
+                                               uint16_t* __restrict__ G1) {
+  constexpr int NI = 2 * kHid;
+  const int sub = threadIdx.x & 7;
+  const int64_t stride = (int64_t)gridDim.x * 32;
+  for (int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 8; i < n; i += stride) {
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int32_t e1 = col_ptr[i + 1];
+    for (int32_t e = col_ptr[i]; e < e1; ++e) {
+      const int32_t j = row_idx[e];
+      const float4* s = reinterpret_cast<const float4*>(U + (size_t)j * NI + kHid + sub * 8);
+      const float4 a = s[0], b = s[1];
+      acc[0] += a.x; acc[1] += a.y; acc[2] += a.z; acc[3] += a.w;
+      acc[4] += b.x; acc[5] += b.y; acc[6] += b.z; acc[7] += b.w;
+    }
+    const float p = pw[i];
+    const float4* s = reinterpret_cast<const float4*>(U + (size_t)i * NI + sub * 8);
+    const float4 a = s[0], b = s[1];
+    const float self[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    float h[8], g[8];
+    unpack8(*reinterpret_cast<const uint4*>(H1 + i * kHid + sub * 8), h);
+    for (int k = 0; k < 8; ++k) g[k] = h[k] > 0.f ? self[k] + p * acc[k] : 0.f;
+    *reinterpret_cast<uint4*>(G1 + i * kHid + sub * 8) = pack8(g);
+  }
+}
+
+// ---- weight gradient: dW = [Z | P Z]^T G and db = sum G, per-block partials ------
+// The reduction runs over nodes, so both operands are staged transposed in LDS
+// ([feature][node], 64 nodes per step) and read as 8-byte MFMA operands.
+// part[block] = [dW (2 FIN x 64, row-major [in][out]), db (64)]
+template <int FIN>
+__global__ void __launch_bounds__(256) k_bwd_w(int64_t n, const uint16_t* __restrict__ Z,
+                                               const uint16_t* __restrict__ AZ,
+                                               const uint16_t* __restrict__ G,
+                                               float* __restrict__ part) {
+  constexpr int K = 2 * FIN, CH = 64, LD = CH + 4;
+  constexpr int TPW = (K / 16) * 4 / 4;  // 16x16 output tiles per wave
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[K * LD];
+  __shared__ __attribute__((aligned(16))) uint16_t sG[kHid * LD];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  f32x4 acc[TPW];
+  for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db = 0.f;
+  const int64_t chunks = (n + CH - 1) / CH;
+  for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+    const int64_t base = ch * CH;
+    for (int t = threadIdx.x; t < CH * (K / 8); t += 256) {
+      const int nd = t / (K / 8), kin = (t % (K / 8)) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (base + nd < n)
+        v = kin < FIN ? *reinterpret_cast<const uint4*>(Z + (base + nd) * FIN + kin)
+                      : *reinterpret_cast<const uint4*>(AZ + (base + nd) * FIN + kin - FIN);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+      for (int k = 0; k < 4; ++k) {
+        sZ[(kin + 2 * k) * LD + nd] = (uint16_t)(w4[k] & 0xFFFFu);
+        sZ[(kin + 2 * k + 1) * LD + nd] = (uint16_t)(w4[k] >> 16);
+      }
+    }
+    for (int t = threadIdx.x; t < CH * (kHid / 8); t += 256) {
+      const int nd = t / (kHid / 8), o = (t % (kHid / 8)) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (base + nd < n) v = *reinterpret_cast<const uint4*>(G + (base + nd) * kHid + o);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+      for (int k = 0; k < 4; ++k) {
+        sG[(o + 2 * k) * LD + nd] = (uint16_t)(w4[k] & 0xFFFFu);
+        sG[(o + 2 * k + 1) * LD + nd] = (uint16_t)(w4[k] >> 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < CH / 16; ++ks) {
+      const int kb = ks * 16 + q * 4;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave * TPW + t, mb = tile / 4, nb = tile % 4;
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(&sZ[(mb * 16 + r) * LD + kb]);
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sG[(nb * 16 + r) * LD + kb]);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    if (threadIdx.x < kHid)
+      for (int nd = 0; nd < CH; ++nd) db += bf2f(sG[threadIdx.x * LD + nd]);
+    __syncthreads();
+  }
+  float* P = part + (size_t)blockIdx.x * (K * kHid + kHid);
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave * TPW + t, mb = tile / 4, nb = tile % 4;
+    for (int i = 0; i < 4; ++i) P[(mb * 16 + 4 * q + i) * kHid + nb * 16 + r] = acc[t][i];
+  }
+  if (threadIdx.x < kHid) P[K * kHid + threadIdx.x] = db;
+}
+
+// sum per-block partials (FP64 accumulation) into canonical gradient slots.
+// mode 0: layer 2 ([128][64] + 64 map to W2s, W2n, b2 contiguously)
+// mode 1: layer 1 (rows 0..7 -> W1s, 16..23 -> W1n, padding rows dropped; bias -> b1)
+// mode 2: head ([64] -> w3, [64] -> b3, [65] -> loss)
+__global__ void k_reduce(const float* __restrict__ part, int nblk, int stride, int count, int mode,
+                         float* __restrict__ grad, double* __restrict__ loss) {
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < count; p += gridDim.x * 256) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * stride + p];
+    int dst = -1;
+    if (mode == 0) {
+      dst = oW2s + p;
+    } else if (mode == 1) {
+      if (p < 2 * kF0 * kHid) {
+        const int row = p / kHid, o = p % kHid;
+        if (row < 8) dst = oW1s + row * kHid + o;
+        else if (row >= kF0 && row < kF0 + 8) dst = oW1n + (row - kF0) * kHid + o;
+      } else {
+        dst = ob1 + (p - 2 * kF0 * kHid);
+      }
+    } else {
+      if (p < kHid) dst = ow3 + p;
+      else if (p == kHid) dst = ob3;
+      else *loss = s;
+    }
+    if (dst >= 0) grad[dst] = (float)s;
+  }
+}
+
+// ---- parameters --------------------------------------------------------------
+__global__ void k_pack(const float* __restrict__ th, uint16_t* __restrict__ W1f,
+                       uint16_t* __restrict__ W2f, uint16_t* __restrict__ W2b,
+                       float* __restrict__ small) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < 2 * kHid * kHid + 2 * kF0 * kHid + kSmall;
+       t += gridDim.x * 256) {
+    if (t < 2 * kHid * kHid) {  // layer 2, forward [o][k] and natural [k][o]
+      const int o = t / (2 * kHid), k = t % (2 * kHid);
+      const float v = k < kHid ? th[oW2s + k * kHid + o] : th[oW2n + (k - kHid) * kHid + o];
+      const uint16_t h = f2bf(v);
+      W2f[o * 2 * kHid + k] = h;
+      W2b[k * kHid + o] = h;
+    } else if (t < 2 * kHid * kHid + 2 * kF0 * kHid) {  // layer 1, forward [o][k], padded
+      const int u = t - 2 * kHid * kHid;
+      const int o = u / (2 * kF0), k = u % (2 * kF0);
+      float v = 0.f;
+      if (k < 8) v = th[oW1s + k * kHid + o];
+      else if (k >= kF0 && k < kF0 + 8) v = th[oW1n + (k - kF0) * kHid + o];
+      W1f[o * 2 * kF0 + k] = f2bf(v);
+    } else {  // b1, b2, w3, b3
+      const int u = t - 2 * kHid * kHid - 2 * kF0 * kHid;
+      const int src = u < kHid ? ob1 + u : u < 2 * kHid ? ob2 + u - kHid : u < 3 * kHid ? ow3 + u - 2 * kHid : ob3;
+      small[u] = bf2f(f2bf(th[src]));
+    }
+  }
+}
+
+// Adam (Kingma and Ba, 2015, Algorithm 1) on the FP32 master weights
+__global__ void k_adam(int np, float* __restrict__ th, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2) {
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < np; t += gridDim.x * 256) {
+    const float gt = g[t];
+    const float mt = b1 * m[t] + (1.f - b1) * gt;
+    const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    th[t] -= lr * (mt / bc1) / (sqrtf(vt / bc2) + eps);
+  }
+}
+
+// ---- targets and warm start ----------------------------------------------------------
+__global__ void k_dsum(int64_t n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_targets(int64_t n, const double* __restrict__ h, double scale, double inv_sum,
+                          float* __restrict__ y, float* __restrict__ w) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double v = h[i];
+    y[i] = v > 0 ? (float)log(scale * v) : 0.f;
+    w[i] = v > 0 ? (float)(v * inv_sum) : 0.f;
+  }
+}
+
+__global__ void k_xhat(int64_t n, const float* __restrict__ yhat, double scale, double* __restrict__ h0) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    h0[i] = scale * exp((double)yhat[i]);
+}
+
+// scales of the start: 0 (cold) and 0.50, 0.55, ..., 1.50
+constexpr int kScales = 22;
+__host__ __device__ inline double scale_of(int k) { return k == 0 ? 0.0 : 0.5 + 0.05 * (k - 1); }
+
+// ||B + c_k r||_1 for every scale, r = F - B with F = B + (P - I) xhat, one pass
+__global__ void __launch_bounds__(256) k_l1grid(int64_t n, const double* __restrict__ b,
+                                                const float* __restrict__ f,
+                                                double* __restrict__ part) {
+  __shared__ double red[kScales][257];
+  double s[kScales];
+  for (int k = 0; k < kScales; ++k) s[k] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double bi = b[i], ri = (double)f[i] - bi;
+    for (int k = 0; k < kScales; ++k) s[k] += fabs(bi + scale_of(k) * ri);
+  }
+  for (int k = 0; k < kScales; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < kScales; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < kScales) part[blockIdx.x * kScales + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_scale(int64_t n, double* __restrict__ h, double c) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    h[i] *= c;
+}
+
+__global__ void k_cold(int64_t n, const double* __restrict__ b, double* __restrict__ h,
+                       float* __restrict__ f) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    h[i] = 0.0;
+    f[i] = (float)b[i];
+  }
+}
+
+// He-normal initial weights from SplitMix64 draws (Box-Muller), zero biases; the
+// head starts near z = 1 (small w3, b3 = 1) so the first predictions lie in the
+// range of the targets
+void init_params(uint64_t seed, std::vector<float>& th) {
+  th.assign(kNP, 0.f);
+  uint64_t state = seed;
+  auto next = [&]() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  };
+  auto normal = [&]() {
+    const double u1 = next(), u2 = next();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+  };
+  for (int k = 0; k < 2 * 8 * kHid; ++k) th[oW1s + k] = (float)(normal() * std::sqrt(2.0 / 16));
+  for (int k = 0; k < 2 * kHid * kHid; ++k) th[oW2s + k] = (float)(normal() * std::sqrt(2.0 / 128));
+  for (int k = 0; k < kHid; ++k) th[ow3 + k] = (float)(normal() * 0.1 * std::sqrt(1.0 / kHid));
+  th[ob3] = 1.f;
+}
+
+}  // namespace
+
+struct ditr_gnn {
+  ditr_ctx* ctx = nullptr;
+  int device = 0;
+  int block = 1000;
+  float* theta = nullptr;  // [kNP] FP32 master weights, canonical order
+  float* mom1 = nullptr;
+  float* mom2 = nullptr;
+  float* grad = nullptr;
+  int64_t step = 0;
+  uint16_t* W1f = nullptr;  // [64][32]
+  uint16_t* W2f = nullptr;  // [64][128]
+  uint16_t* W2b = nullptr;  // [128][64]
+  float* small = nullptr;   // b1, b2, w3, b3 (BF16-rounded values)
+  float* part = nullptr;    // weight-gradient partials
+  float* hpart = nullptr;   // heavy-chunk partials [chunks][64]
+  int64_t hpart_cap = 0;
+  double* dpart = nullptr;  // FP64 reduction partials [kSumBlocks][3]
+  double* loss = nullptr;   // device FP64
+  int64_t cap = 0;          // nodes the activation buffers hold
+  uint16_t *X = nullptr, *AX = nullptr, *H1 = nullptr, *A1 = nullptr, *H2 = nullptr;
+  uint16_t *G1 = nullptr, *G2 = nullptr;
+  float* yhat = nullptr;
+  float* zh = nullptr;      // head pre-activation z
+  float* U = nullptr;
+};
+
+namespace {
+
+void free_acts(ditr_gnn* m) {
+  for (void* p : {(void*)m->X, (void*)m->AX, (void*)m->H1, (void*)m->A1, (void*)m->H2,
+                  (void*)m->G1, (void*)m->G2, (void*)m->yhat, (void*)m->zh, (void*)m->U})
+    (void)hipFree(p);
+  m->X = m->AX = m->H1 = m->A1 = m->H2 = m->G1 = m->G2 = nullptr;
+  m->yhat = m->zh = m->U = nullptr;
+  m->cap = 0;
+}
+
+// activation buffers for n nodes; `train` adds the backward ones
+int ensure(ditr_gnn* m, const ditr_graph* g, bool train) {
+  const int64_t n = g->n;
+  if (m->cap < n || (train && !m->U)) {
+    const int64_t cap = std::max(n, m->cap);
+    free_acts(m);
+    bool ok = hipMalloc((void**)&m->X, sizeof(uint16_t) * cap * kF0) == hipSuccess &&
+              hipMalloc((void**)&m->AX, sizeof(uint16_t) * cap * kF0) == hipSuccess &&
+              hipMalloc((void**)&m->H1, sizeof(uint16_t) * cap * kHid) == hipSuccess &&
+              hipMalloc((void**)&m->A1, sizeof(uint16_t) * cap * kHid) == hipSuccess &&
+              hipMalloc((void**)&m->H2, sizeof(uint16_t) * cap * kHid) == hipSuccess &&
+              hipMalloc((void**)&m->yhat, sizeof(float) * cap) == hipSuccess &&
+              hipMalloc((void**)&m->zh, sizeof(float) * cap) == hipSuccess;
+    if (ok && train)
+      ok = hipMalloc((void**)&m->G1, sizeof(uint16_t) * cap * kHid) == hipSuccess &&
+           hipMalloc((void**)&m->G2, sizeof(uint16_t) * cap * kHid) == hipSuccess &&
+           hipMalloc((void**)&m->U, sizeof(float) * cap * 2 * kHid) == hipSuccess;
+    if (!ok) {
+      free_acts(m);
+      (void)hipGetLastError();
+      return set_error(DITR_ENOMEM, "device allocation failed (network activations, n = %lld)",
+                       (long long)n);
+    }
+    m->cap = cap;
+  }
+  if (m->hpart_cap < g->n_chunks) {
+    (void)hipFree(m->hpart);
+    m->hpart = nullptr;
+    m->hpart_cap = 0;
+    HIP_TRY(hipMalloc((void**)&m->hpart, sizeof(float) * (size_t)g->n_chunks * kHid));
+    m->hpart_cap = g->n_chunks;
+  }
+  return DITR_OK;
+}
+
+template <int F>
+int aggregate(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const uint16_t* Z, uint16_t* out) {
+  hipStream_t st = c->stream;
+  k_agg<F><<<grid_of(g->n * (F / 8), 256, 16384), 256, 0, st>>>(g->n, g->row_ptr, g->csr_col,
+                                                                 g->pp.pw, Z, out);
+  if (g->n_chunks > 0) {
+    k_agg_heavy<F><<<g->n_chunks, 256, 0, st>>>(g->chunk_beg, g->chunk_end, g->csr_col, g->pp.pw, Z,
+                                                m->hpart);
+    k_agg_heavy_fin<F><<<grid_of((int64_t)g->n_heavy * F, 256, 4096), 256, 0, st>>>(
+        g->n_heavy, g->heavy_rows, g->chunk_h, g->n_chunks, m->hpart, out);
+  }
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+int forward(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g) {
+  hipStream_t st = c->stream;
+  const int64_t n = g->n;
+  k_features<<<grid_of(n, 256, 8192), 256, 0, st>>>(n, g->col_ptr, g->row_ptr, m->block, m->X);
+  HIP_TRY(hipGetLastError());
+  int rc = aggregate<kF0>(c, m, g, m->X, m->AX);
+  if (rc) return rc;
+  const int gd = grid_of((n + 63) / 64, 1, 2048);
+  k_dense<kF0, false><<<gd, 256, 0, st>>>(n, m->X, m->AX, m->W1f, m->small, nullptr, nullptr, m->H1,
+                                          nullptr, nullptr);
+  HIP_TRY(hipGetLastError());
+  rc = aggregate<kHid>(c, m, g, m->H1, m->A1);
+  if (rc) return rc;
+  k_dense<kHid, true><<<gd, 256, 0, st>>>(n, m->H1, m->A1, m->W2f, m->small + kHid,
+                                          m->small + 2 * kHid, m->small + 3 * kHid, m->H2, m->zh, m->yhat);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+// forward + backward; gradient into m->grad, loss into m->loss (device)
+int backward(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* y, const float* w) {
+  hipStream_t st = c->stream;
+  const int64_t n = g->n;
+  int rc = forward(c, m, g);
+  if (rc) return rc;
+  k_head_bwd<<<kHeadBlocks, 256, 0, st>>>(n, m->H2, m->zh, m->yhat, y, w, m->small + 2 * kHid, m->G2,
+                                          m->part);
+  k_reduce<<<1, 256, 0, st>>>(m->part, kHeadBlocks, kHid + 2, kHid + 2, 2, m->grad, m->loss);
+  k_bwd_w<kHid><<<kBwdBlocks, 256, 0, st>>>(n, m->H1, m->A1, m->G2, m->part);
+  k_reduce<<<grid_of(2 * kHid * kHid + kHid, 256, 64), 256, 0, st>>>(
+      m->part, kBwdBlocks, 2 * kHid * kHid + kHid, 2 * kHid * kHid + kHid, 0, m->grad, nullptr);
+  const int gd = grid_of((n + 63) / 64, 1, 2048);
+  k_bwd_data<<<gd, 256, 0, st>>>(n, m->G2, m->W2b, m->U);
+  k_agg_t<<<grid_of(n * 8, 256, 16384), 256, 0, st>>>(n, g->col_ptr, g->row_idx, g->pp.pw, m->U, m->H1,
+                                                       m->G1);
+  k_bwd_w<kF0><<<kBwdBlocks, 256, 0, st>>>(n, m->X, m->AX, m->G1, m->part);
+  k_reduce<<<grid_of(2 * kF0 * kHid + kHid, 256, 64), 256, 0, st>>>(
+      m->part, kBwdBlocks, 2 * kF0 * kHid + kHid, 2 * kF0 * kHid + kHid, 1, m->grad, nullptr);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+int repack(ditr_ctx* c, ditr_gnn* m) {
+  k_pack<<<64, 256, 0, c->stream>>>(m->theta, m->W1f, m->W2f, m->W2b, m->small);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+int check_net(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g) {
+  if (!c || !m || !g) return set_error(DITR_EINVAL, "NULL argument");
+  if (m->ctx != c || g->ctx != c) return set_error(DITR_EINVAL, "network and graph must use this context");
+  if (!g->pp.ready) return set_error(DITR_EINVAL, "graph has no partition tables");
+  return DITR_OK;
+}
+
+int dsum(ditr_ctx* c, ditr_gnn* m, int64_t n, const double* x, double* out) {
+  const int nb = grid_of(n, 256, kSumBlocks);
+  k_dsum<<<nb, 256, 0, c->stream>>>(n, x, m->dpart);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h(nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), m->dpart, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double s = 0;
+  for (double v : h) s += v;
+  *out = s;
+  return DITR_OK;
+}
+
+int ctrl_sum_abs(ditr_ctx* c, double* out) {
+  HIP_TRY(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *out = c->ctrl_host->sum_abs;
+  return DITR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ditr_gnn_create(ditr_ctx* c, ditr_gnn** out, int hidden, int block, uint64_t seed) {
+  if (!c || !out) return set_error(DITR_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (hidden != kHid) return set_error(DITR_EINVAL, "hidden width must be %d", kHid);
+  if (block < 1) return set_error(DITR_EINVAL, "block must be >= 1");
+  HIP_TRY(hipSetDevice(c->device));
+  ditr_gnn* m = new (std::nothrow) ditr_gnn();
+  if (!m) return set_error(DITR_ENOMEM, "host allocation failed");
+  m->ctx = c;
+  m->device = c->device;
+  m->block = block;
+  const size_t pb = sizeof(float) * kNP;
+  const size_t part_floats = (size_t)std::max(kBwdBlocks * (2 * kHid * kHid + kHid),
+                                              kHeadBlocks * (kHid + 2));
+  bool ok = hipMalloc((void**)&m->theta, pb) == hipSuccess &&
+            hipMalloc((void**)&m->mom1, pb) == hipSuccess &&
+            hipMalloc((void**)&m->mom2, pb) == hipSuccess &&
+            hipMalloc((void**)&m->grad, pb) == hipSuccess &&
+            hipMalloc((void**)&m->W1f, sizeof(uint16_t) * kHid * 2 * kF0) == hipSuccess &&
+            hipMalloc((void**)&m->W2f, sizeof(uint16_t) * kHid * 2 * kHid) == hipSuccess &&
+            hipMalloc((void**)&m->W2b, sizeof(uint16_t) * kHid * 2 * kHid) == hipSuccess &&
+            hipMalloc((void**)&m->small, sizeof(float) * kSmall) == hipSuccess &&
+            hipMalloc((void**)&m->part, sizeof(float) * part_floats) == hipSuccess &&
+            hipMalloc((void**)&m->dpart, sizeof(double) * kScales * kSumBlocks) == hipSuccess &&
+            hipMalloc((void**)&m->loss, sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    ditr_gnn_destroy(m);
+    return set_error(DITR_ENOMEM, "device allocation failed (network)");
+  }
+  std::vector<float> th;
+  init_params(seed, th);
+  int rc = ditr_gnn_set_params(m, th.data());
+  if (rc) {
+    ditr_gnn_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return DITR_OK;
+}
+
+int ditr_gnn_destroy(ditr_gnn* m) {
+  if (!m) return DITR_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  free_acts(m);
+  for (void* p : {(void*)m->theta, (void*)m->mom1, (void*)m->mom2, (void*)m->grad, (void*)m->W1f,
+                  (void*)m->W2f, (void*)m->W2b, (void*)m->small, (void*)m->part, (void*)m->hpart,
+                  (void*)m->dpart, (void*)m->loss})
+    (void)hipFree(p);
+  delete m;
+  return DITR_OK;
+}
+
+int ditr_gnn_get_params(ditr_gnn* m, float* h_theta) {
+  if (!m || !h_theta) return set_error(DITR_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(h_theta, m->theta, sizeof(float) * kNP, hipMemcpyDeviceToHost, m->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(m->ctx->stream));
+  return DITR_OK;
+}
+
+int ditr_gnn_set_params(ditr_gnn* m, const float* h_theta) {
+  if (!m || !h_theta) return set_error(DITR_EINVAL, "NULL argument");
+  for (int k = 0; k < kNP; ++k)
+    if (!std::isfinite(h_theta[k])) return set_error(DITR_ENONFINITE, "parameter %d is not finite", k);
+  ditr_ctx* c = m->ctx;
+  HIP_TRY(hipMemcpyAsync(m->theta, h_theta, sizeof(float) * kNP, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(m->mom1, 0, sizeof(float) * kNP, c->stream));
+  HIP_TRY(hipMemsetAsync(m->mom2, 0, sizeof(float) * kNP, c->stream));
+  m->step = 0;
+  int rc = repack(c, m);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return DITR_OK;
+}
+
+int ditr_gnn_forward(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, float* d_yhat) {
+  int rc = check_net(c, m, g);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(c->device));
+  rc = ensure(m, g, false);
+  if (!rc) rc = forward(c, m, g);
+  if (rc) return rc;
+  if (d_yhat)
+    HIP_TRY(hipMemcpyAsync(d_yhat, m->yhat, sizeof(float) * g->n, hipMemcpyDeviceToDevice, c->stream));
+  return DITR_OK;
+}
+
+int ditr_gnn_activation(ditr_ctx* c, const ditr_gnn* m, int which, int64_t n, uint16_t* d_out) {
+  if (!c || !m || !d_out) return set_error(DITR_EINVAL, "NULL argument");
+  if (n < 0 || n > m->cap) return set_error(DITR_EINVAL, "n exceeds the activations held");
+  const uint16_t* src = nullptr;
+  int width = kHid;
+  switch (which) {
+    case DITR_GNN_ACT_X: src = m->X; width = kF0; break;
+    case DITR_GNN_ACT_PX: src = m->AX; width = kF0; break;
+    case DITR_GNN_ACT_H1: src = m->H1; break;
+    case DITR_GNN_ACT_PH1: src = m->A1; break;
+    case DITR_GNN_ACT_H2: src = m->H2; break;
+    default: return set_error(DITR_EINVAL, "unknown activation %d", which);
+  }
+  if (!src) return set_error(DITR_EINVAL, "no forward pass has run");
+  HIP_TRY(hipMemcpyAsync(d_out, src, sizeof(uint16_t) * n * width, hipMemcpyDeviceToDevice, c->stream));
+  return DITR_OK;
+}
+
+int ditr_gnn_targets(ditr_ctx* c, const ditr_graph* g, const double* d_h, double b_l1, float* d_y,
+                     float* d_w) {
+  if (!c || !g || !d_h || !d_y || !d_w) return set_error(DITR_EINVAL, "NULL argument");
+  if (!(b_l1 > 0) || !std::isfinite(b_l1)) return set_error(DITR_EINVAL, "b_l1 must be > 0");
+  HIP_TRY(hipSetDevice(c->device));
+  const int64_t n = g->n;
+  const int nb = grid_of(n, 256, kSumBlocks);
+  double* part = nullptr;
+  HIP_TRY(hipMalloc((void**)&part, sizeof(double) * nb));
+  k_dsum<<<nb, 256, 0, c->stream>>>(n, d_h, part);
+  std::vector<double> h(nb);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(part);
+  HIP_TRY(e);
+  double s = 0;
+  for (double v : h) s += v;
+  if (!(s > 0) || !std::isfinite(s)) return set_error(DITR_EINVAL, "sum of H must be positive and finite");
+  k_targets<<<grid_of(n, 256, 8192), 256, 0, c->stream>>>(n, d_h, (double)n / b_l1, 1.0 / s, d_y, d_w);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+int ditr_gnn_grad(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* d_y, const float* d_w,
+                  float* d_grad, double* h_loss) {
+  int rc = check_net(c, m, g);
+  if (rc) return rc;
+  if (!d_y || !d_w) return set_error(DITR_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(c->device));
+  rc = ensure(m, g, true);
+  if (!rc) rc = backward(c, m, g, d_y, d_w);
+  if (rc) return rc;
+  if (d_grad)
+    HIP_TRY(hipMemcpyAsync(d_grad, m->grad, sizeof(float) * kNP, hipMemcpyDeviceToDevice, c->stream));
+  if (h_loss) {
+    HIP_TRY(hipMemcpyAsync(h_loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return DITR_OK;
+}
+
+int ditr_gnn_train_step(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* d_y,
+                        const float* d_w, double lr, double* h_loss) {
+  if (!(lr > 0) || !std::isfinite(lr)) return set_error(DITR_EINVAL, "lr must be > 0");
+  int rc = ditr_gnn_grad(c, m, g, d_y, d_w, nullptr, nullptr);
+  if (rc) return rc;
+  m->step += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const double bc1 = 1 - std::pow(b1, (double)m->step), bc2 = 1 - std::pow(b2, (double)m->step);
+  k_adam<<<grid_of(kNP, 256, 64), 256, 0, c->stream>>>(kNP, m->theta, m->grad, m->mom1, m->mom2,
+                                                       (float)lr, (float)b1, (float)b2, 1e-8f,
+                                                       (float)bc1, (float)bc2);
+  HIP_TRY(hipGetLastError());
+  rc = repack(c, m);
+  if (rc) return rc;
+  if (h_loss) {
+    HIP_TRY(hipMemcpyAsync(h_loss, m->loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return DITR_OK;
+}
+
+int ditr_gnn_predict_h0(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const double* d_b,
+                        double* d_h0, float* d_f0, ditr_gnn_start* info) {
+  const double t0 = wall_now();
+  int rc = check_net(c, m, g);
+  if (rc) return rc;
+  if (!d_b || !d_h0 || !d_f0) return set_error(DITR_EINVAL, "NULL argument");
+  HIP_TRY(hipSetDevice(c->device));
+  ditr_gnn_start st;
+  memset(&st, 0, sizeof(st));
+  const int64_t n = g->n;
+  rc = ensure(m, g, false);
+  if (rc) return rc;
+  // ||B||_1 (B >= 0 is not assumed: sum of |B_i|)
+  rc = launch_norm_f64(c, n, d_b);
+  if (!rc) rc = ctrl_sum_abs(c, &st.b_l1);
+  if (rc) return rc;
+  if (!std::isfinite(st.b_l1)) return set_error(DITR_ENONFINITE, "B holds NaN or Inf");
+  const int gb = grid_of(n, 256, 8192);
+  if (!(st.b_l1 > 0)) {  // B = 0: X = 0
+    k_cold<<<gb, 256, 0, c->stream>>>(n, d_b, d_h0, d_f0);
+    HIP_TRY(hipGetLastError());
+    st.fell_back = 1;
+    st.seconds = wall_now() - t0;
+    if (info) *info = st;
+    return DITR_OK;
+  }
+  rc = forward(c, m, g);
+  if (rc) return rc;
+  k_xhat<<<gb, 256, 0, c->stream>>>(n, m->yhat, st.b_l1 / (double)n, d_h0);
+  HIP_TRY(hipGetLastError());
+  // F = B + (P - I) xhat; the scale c (0 = cold start) minimizing ||B + c r||_1, r = F - B
+  rc = launch_refresh(c, g, d_b, d_h0, d_f0);
+  if (rc) return rc;
+  const int nb = grid_of(n, 256, kSumBlocks);
+  k_l1grid<<<nb, 256, 0, c->stream>>>(n, d_b, d_f0, m->dpart);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h((size_t)kScales * nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), m->dpart, sizeof(double) * kScales * nb, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int best = 0;
+  double best_l1 = INFINITY;
+  for (int k = 0; k < kScales; ++k) {
+    double l1 = 0;
+    for (int q = 0; q < nb; ++q) l1 += h[(size_t)q * kScales + k];
+    if (l1 < best_l1) {
+      best_l1 = l1;
+      best = k;
+    }
+  }
+  const double cs = scale_of(best);
+  st.scale_c = cs;
+  bool cold = best == 0 || !std::isfinite(best_l1);
+  if (!cold) {
+    k_scale<<<gb, 256, 0, c->stream>>>(n, d_h0, cs);
+    HIP_TRY(hipGetLastError());
+    rc = launch_refresh(c, g, d_b, d_h0, d_f0);
+    if (!rc) rc = ctrl_sum_abs(c, &st.f0_l1);
+    if (rc) return rc;
+    cold = !(st.f0_l1 <= st.b_l1);
+  }
+  if (cold) {  // H_0 = 0 leaves the least fluid
+    k_cold<<<gb, 256, 0, c->stream>>>(n, d_b, d_h0, d_f0);
+    HIP_TRY(hipGetLastError());
+    st.fell_back = 1;
+    st.scale_c = 0;
+    st.f0_l1 = st.b_l1;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  st.seconds = wall_now() - t0;
+  if (info) *info = st;
+  return DITR_OK;
+}
+
+}  // extern "C"

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import weakref
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libditr.so")
@@ -20,6 +21,8 @@ EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
 PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
+GNN_PARAMS = 9409
+GNN_ACT_X, GNN_ACT_PX, GNN_ACT_H1, GNN_ACT_PH1, GNN_ACT_H2 = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "ABORTED", 3: "NOT_FOUND", -1: "EINVAL", -2: "EGRAPH",
                  -3: "ENOMEM", -4: "EHIP", -5: "ENONFINITE"}
@@ -90,6 +93,20 @@ class TuneInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GnnStart(ctypes.Structure):
+    _fields_ = [
+        ("b_l1", ctypes.c_double),
+        ("scale_c", ctypes.c_double),
+        ("f0_l1", ctypes.c_double),
+        ("fell_back", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -118,6 +135,16 @@ _SIGNATURES = {
     "ditr_tune_cache_get": ([ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts)], _i32),
     "ditr_tune_cache_put": ([ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts), _dbl, _dbl],
                             _i32),
+    "ditr_gnn_create": ([_vp, ctypes.POINTER(_vp), _i32, _i32, ctypes.c_uint64], _i32),
+    "ditr_gnn_destroy": ([_vp], _i32),
+    "ditr_gnn_get_params": ([_vp, _vp], _i32),
+    "ditr_gnn_set_params": ([_vp, _vp], _i32),
+    "ditr_gnn_forward": ([_vp, _vp, _vp, _vp], _i32),
+    "ditr_gnn_activation": ([_vp, _vp, _i32, _i64, _vp], _i32),
+    "ditr_gnn_targets": ([_vp, _vp, _vp, _dbl, _vp, _vp], _i32),
+    "ditr_gnn_grad": ([_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)], _i32),
+    "ditr_gnn_train_step": ([_vp, _vp, _vp, _vp, _vp, _dbl, ctypes.POINTER(_dbl)], _i32),
+    "ditr_gnn_predict_h0": ([_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(GnnStart)], _i32),
 }
 
 
@@ -183,12 +210,15 @@ class Context:
         h = ctypes.c_void_p()
         check(lib().ditr_create(ctypes.byref(h), device, s))
         self.handle = h
+        self._children = weakref.WeakSet()  # graphs and networks, closed first
 
     def abort(self):
         check(lib().ditr_abort(self.handle))
 
     def close(self):
         if self.handle:
+            for child in list(self._children):
+                child.close()
             lib().ditr_destroy(self.handle)
             self.handle = None
 
@@ -219,6 +249,7 @@ class Graph:
                                       _ptr(self.col_ptr), _ptr(self.row_idx) if self.nnz else None,
                                       damping, ctypes.byref(o)))
         self.handle = h
+        ctx._children.add(self)
 
     def partitions(self):
         import numpy as np
@@ -351,3 +382,94 @@ def tune_cache_put(path: str, key: int, o: Opts, seconds: float = 0.0,
                    default_seconds: float = 0.0):
     """ditr_tune_cache_put: add or replace the entry under `key`."""
     check(lib().ditr_tune_cache_put(path.encode(), key, ctypes.byref(o), seconds, default_seconds))
+
+
+def gnn_targets(ctx: Context, g: Graph, h, b_l1: float, y=None, w=None):
+    """ditr_gnn_targets: (y, w) FP32 device vectors from a solved H."""
+    torch = ctx.torch
+    if h.dtype != torch.float64 or h.numel() != g.n or not (h.is_cuda and h.is_contiguous()):
+        raise ValueError("h must be a contiguous float64 device vector of length n")
+    y = torch.empty(g.n, dtype=torch.float32, device=h.device) if y is None else y
+    w = torch.empty(g.n, dtype=torch.float32, device=h.device) if w is None else w
+    check(lib().ditr_gnn_targets(ctx.handle, g.handle, _ptr(h), b_l1, _ptr(y), _ptr(w)))
+    return y, w
+
+
+class Gnn:
+    """ditr_gnn: the warm-start network (hidden width 64)."""
+
+    def __init__(self, ctx: Context, block: int = 1000, seed: int = 7, hidden: int = 64):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        check(lib().ditr_gnn_create(ctx.handle, ctypes.byref(h), hidden, block, seed))
+        self.handle = h
+        ctx._children.add(self)
+
+    def get_params(self):
+        import numpy as np
+
+        out = np.empty(GNN_PARAMS, np.float32)
+        check(lib().ditr_gnn_get_params(self.handle, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def set_params(self, theta):
+        import numpy as np
+
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != GNN_PARAMS:
+            raise ValueError("expected %d parameters" % GNN_PARAMS)
+        check(lib().ditr_gnn_set_params(self.handle, ctypes.c_void_p(t.ctypes.data)))
+
+    def forward(self, g: Graph, yhat=None):
+        torch = self.ctx.torch
+        dev = g.col_ptr.device
+        yhat = torch.empty(g.n, dtype=torch.float32, device=dev) if yhat is None else yhat
+        check(lib().ditr_gnn_forward(self.ctx.handle, self.handle, g.handle, _ptr(yhat)))
+        return yhat
+
+    def activation(self, which: int, n: int):
+        """A BF16 activation of the last forward pass as a [n, width] tensor."""
+        torch = self.ctx.torch
+        width = 16 if which in (GNN_ACT_X, GNN_ACT_PX) else 64
+        out = torch.empty((n, width), dtype=torch.bfloat16, device="cuda:%d" % self.ctx.device)
+        check(lib().ditr_gnn_activation(self.ctx.handle, self.handle, which, n, _ptr(out)))
+        return out
+
+    def grad(self, g: Graph, y, w):
+        """(loss, gradient) at the current weights; gradient is an FP32 device vector."""
+        torch = self.ctx.torch
+        gr = torch.empty(GNN_PARAMS, dtype=torch.float32, device=y.device)
+        loss = ctypes.c_double()
+        check(lib().ditr_gnn_grad(self.ctx.handle, self.handle, g.handle, _ptr(y), _ptr(w),
+                                  _ptr(gr), ctypes.byref(loss)))
+        return loss.value, gr
+
+    def train_step(self, g: Graph, y, w, lr: float, want_loss: bool = True):
+        loss = ctypes.c_double()
+        check(lib().ditr_gnn_train_step(self.ctx.handle, self.handle, g.handle, _ptr(y), _ptr(w),
+                                        lr, ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def predict_h0(self, g: Graph, b, h0, f0) -> GnnStart:
+        """ditr_gnn_predict_h0: H_0 into h0 (FP64) and its exact fluid into f0 (FP32)."""
+        torch = self.ctx.torch
+        if b.dtype != torch.float64 or h0.dtype != torch.float64 or f0.dtype != torch.float32:
+            raise TypeError("b, h0 must be float64 and f0 float32")
+        for t in (b, h0, f0):
+            if t.numel() != g.n or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("b, h0, f0 must be contiguous device vectors of length n")
+        info = GnnStart()
+        check(lib().ditr_gnn_predict_h0(self.ctx.handle, self.handle, g.handle, _ptr(b), _ptr(h0),
+                                        _ptr(f0), ctypes.byref(info)))
+        return info
+
+    def close(self):
+        if self.handle:
+            lib().ditr_gnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,308 @@
+"""GPU parity of the warm-start network against the FP64 oracle (oracle/gnn.py)
+and the gain test of the learned start.
+
+Layer by layer, each GPU stage is compared with the definition evaluated in
+FP64 on the GPU's own BF16 inputs and BF16-rounded weights, so the only
+differences are accumulation order and the BF16 rounding of the output; the
+whole forward pass and the gradient are compared with the oracle run from
+exact FP64 features (BF16 tolerance: relative L2 <= 2e-2, cosine >= 0.999).
+"""
+import numpy as np
+import pytest
+
+import ditgen
+import oracle
+from oracle import gnn as og
+from conftest import D
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1202_6168_amd import ditr  # noqa: E402
+
+BF_EPS = 2.0 ** -8  # relative spacing of BF16 (8 significant bits)
+
+
+def bf16_round(x):
+    """FP32 -> BF16 (round to nearest even) -> FP64."""
+    a = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) >> 16
+    return (a.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def act(net, which, n):
+    return net.activation(which, n).float().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ditr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def case(ctx):
+    """A 5e4-node generated graph (its hub spans two 2048-link chunks), a
+    freshly initialized network after one forward pass, and solved targets."""
+    spec = ditgen.GraphSpec(n=50_000, block=1000, seed=77)
+    cp, ri = ditgen.generate(spec)
+    dev = torch.device("cuda", 0)
+    cpt, rit = torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)
+    g = ditr.Graph(ctx, cpt, rit)
+    indeg = np.bincount(ri, minlength=spec.n)
+    assert indeg.max() > 2048  # a heavy row is summed from more than one chunk
+    net = ditr.Gnn(ctx, block=1000, seed=7)
+    yhat = net.forward(g).cpu().numpy().astype(np.float64)
+    b = ditgen.uniform_b(spec.n)
+    bt = torch.from_numpy(b).to(dev)
+    ht = torch.empty(spec.n, dtype=torch.float64, device=dev)
+    ft = torch.empty(spec.n, dtype=torch.float32, device=dev)
+    ditr.solve(ctx, g, bt, ht, ft, rel_tol=1e-10, allow=(ditr.OK,))
+    y, w = ditr.gnn_targets(ctx, g, ht, 0.15)
+    return dict(cp=cp, ri=ri, n=spec.n, g=g, keep=(cpt, rit), net=net, yhat=yhat, b=b, bt=bt,
+                h=ht.cpu().numpy(), y=y, w=w, P=og.p_matrix(cp, ri, D))
+
+
+def test_features_match_oracle(case):
+    X = act(case["net"], ditr.GNN_ACT_X, case["n"])
+    Xo = og.features(case["cp"], case["ri"], 1000)
+    assert np.all(X[:, 8:] == 0)
+    # the GPU's log1p is FP32: at most one BF16 step from the rounded FP64 value
+    assert np.all(np.abs(X[:, :8] - bf16_round(Xo)) <= BF_EPS * np.abs(Xo) + 1e-12)
+    assert np.array_equal(X[:, 2:4], Xo[:, 2:4])
+
+
+@pytest.mark.parametrize("which_in,which_out,width", [(ditr.GNN_ACT_X, ditr.GNN_ACT_PX, 16),
+                                                      (ditr.GNN_ACT_H1, ditr.GNN_ACT_PH1, 64)])
+def test_aggregation_matches_operator(case, which_in, which_out, width):
+    n, P = case["n"], case["P"]
+    Z = act(case["net"], which_in, n)
+    A = act(case["net"], which_out, n)
+    ref = P @ Z
+    mag = P @ np.abs(Z)
+    assert np.all(np.abs(A - ref) <= BF_EPS * np.abs(ref) + 1e-5 * mag + 1e-30)
+    assert np.linalg.norm(A - ref) <= 3e-3 * np.linalg.norm(ref)
+
+
+def test_dense_layers_and_head(case):
+    n, net = case["n"], case["net"]
+    p = og.unflatten(bf16_round(net.get_params()))
+    X, AX = act(net, ditr.GNN_ACT_X, n), act(net, ditr.GNN_ACT_PX, n)
+    H1, A1, H2 = act(net, ditr.GNN_ACT_H1, n), act(net, ditr.GNN_ACT_PH1, n), act(net, ditr.GNN_ACT_H2, n)
+    for Zs, Za, Ws, Wn, bias, H in ((X[:, :8], AX[:, :8], p["W1s"], p["W1n"], p["b1"], H1),
+                                    (H1, A1, p["W2s"], p["W2n"], p["b2"], H2)):
+        z = Zs @ Ws + Za @ Wn + bias
+        mag = np.abs(Zs) @ np.abs(Ws) + np.abs(Za) @ np.abs(Wn) + np.abs(bias)
+        ref = np.maximum(z, 0)
+        assert np.all(np.abs(H - ref) <= BF_EPS * np.abs(ref) + 1e-5 * mag)
+        assert 0.05 < (H > 0).mean() < 0.95
+    z = H2 @ p["w3"] + p["b3"][0]
+    ref = np.log(np.maximum(z, 0) + np.log1p(np.exp(-np.abs(z))))
+    mag = np.abs(H2) @ np.abs(p["w3"]) + abs(p["b3"][0])
+    assert np.all(np.abs(case["yhat"] - ref) <= 1e-5 * (1 + np.abs(ref)) + 1e-5 * mag)
+
+
+def test_forward_matches_oracle(case):
+    p = og.unflatten(bf16_round(case["net"].get_params()))
+    Xo = og.features(case["cp"], case["ri"], 1000)
+    ref = og.forward(p, Xo, case["P"])["yhat"]
+    assert np.linalg.norm(case["yhat"] - ref) <= 2e-2 * np.linalg.norm(ref)
+
+
+def test_targets_match_oracle(case):
+    yo, wo = og.targets(case["h"], np.abs(case["b"]).sum())
+    y, w = case["y"].cpu().numpy(), case["w"].cpu().numpy()
+    assert np.allclose(y, yo, rtol=2 ** -23, atol=2 ** -22)
+    assert np.allclose(w, wo, rtol=2 ** -22, atol=0)
+
+
+def test_gradient_matches_oracle(case):
+    net = case["net"]
+    loss, gr = net.grad(case["g"], case["y"], case["w"])
+    p = og.unflatten(bf16_round(net.get_params()))
+    Xo = og.features(case["cp"], case["ri"], 1000)
+    y = case["y"].cpu().numpy().astype(np.float64)
+    w = case["w"].cpu().numpy().astype(np.float64)
+    Lo, go = og.loss_and_grad(p, Xo, case["P"], y, w)
+    assert abs(loss - Lo) <= 2e-2 * Lo
+    gg, gof = gr.cpu().numpy().astype(np.float64), og.flatten(go)
+    cos = gg @ gof / (np.linalg.norm(gg) * np.linalg.norm(gof))
+    assert cos >= 0.999 and np.linalg.norm(gg - gof) <= 2e-2 * np.linalg.norm(gof)
+    k = 0
+    for name, shape in og._SHAPES:
+        s = int(np.prod(shape))
+        a, o = gg[k:k + s], gof[k:k + s]
+        k += s
+        assert a @ o >= 0.99 * np.linalg.norm(a) * np.linalg.norm(o), name
+
+
+def test_adam_step_matches_oracle(ctx, case):
+    net = ditr.Gnn(ctx, block=1000, seed=11)
+    th0 = net.get_params().astype(np.float64)
+    _, gr = net.grad(case["g"], case["y"], case["w"])
+    net.train_step(case["g"], case["y"], case["w"], lr=1e-3)
+    th1 = net.get_params().astype(np.float64)
+    ref, _, _ = og.adam(th0, gr.cpu().numpy().astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    assert np.allclose(th1, ref, rtol=1e-5, atol=1e-7)
+    net.close()
+
+
+def test_params_round_trip_and_errors(ctx):
+    net = ditr.Gnn(ctx, block=100, seed=3)
+    th = np.random.default_rng(0).normal(size=ditr.GNN_PARAMS).astype(np.float32)
+    net.set_params(th)
+    assert np.array_equal(net.get_params(), th)
+    th[5] = np.nan
+    with pytest.raises(ditr.DitrError) as e:
+        net.set_params(th)
+    assert e.value.status == ditr.ENONFINITE
+    net.close()
+    with pytest.raises(ditr.DitrError) as e:
+        ditr.Gnn(ctx, hidden=32)
+    assert e.value.status == ditr.EINVAL
+    a = ditr.Gnn(ctx, seed=5).get_params()
+    assert np.array_equal(a, ditr.Gnn(ctx, seed=5).get_params())
+    assert not np.array_equal(a, ditr.Gnn(ctx, seed=6).get_params())
+
+
+def check_start(case, net, b):
+    """predict_h0 against the oracle's warm start at the GPU's prediction."""
+    n, P = case["n"], case["P"]
+    dev = torch.device("cuda", 0)
+    bt = torch.from_numpy(b).to(dev)
+    h0 = torch.empty(n, dtype=torch.float64, device=dev)
+    f0 = torch.empty(n, dtype=torch.float32, device=dev)
+    info = net.predict_h0(case["g"], bt, h0, f0)
+    yhat = net.forward(case["g"]).cpu().numpy().astype(np.float64)
+    H0, F0 = h0.cpu().numpy(), f0.cpu().numpy().astype(np.float64)
+    b1 = np.abs(b).sum()
+    xhat = np.exp(yhat) * b1 / n
+    r = P @ xhat - xhat
+    l1 = np.array([np.abs(b + c * r).sum() for c in og.SCALES])
+    # the GPU's scale is optimal on the grid up to its FP32 residual
+    k = int(np.argmin(np.abs(og.SCALES - info.scale_c)))
+    assert abs(og.SCALES[k] - info.scale_c) < 1e-12
+    assert l1[k] <= l1.min() * (1 + 1e-5)
+    assert np.allclose(H0, info.scale_c * xhat, rtol=1e-6, atol=0)
+    exact = b + P @ H0 - H0
+    assert np.abs(F0 - exact).max() <= 2 ** -23 * np.abs(exact).max() + 1e-300
+    assert abs(info.f0_l1 - np.abs(exact).sum()) <= 1e-9 * b1
+    assert info.f0_l1 <= b1 * (1 + 1e-12)
+    return info, l1
+
+
+def test_predict_h0_matches_oracle(ctx, case):
+    net = ditr.Gnn(ctx, seed=7)
+    for _ in range(30):
+        net.train_step(case["g"], case["y"], case["w"], lr=3e-3, want_loss=False)
+    info, l1 = check_start(case, net, case["b"])
+    assert abs(info.b_l1 - 0.15) < 1e-12
+    assert info.fell_back == 0 and info.scale_c > 0 and info.f0_l1 < info.b_l1
+    net.close()
+
+
+def test_predict_h0_falls_back_to_cold(ctx, case):
+    # a constant prediction for a one-seed personalization vector: the oracle's
+    # grid says no scaled start beats B, and so must the GPU
+    net = ditr.Gnn(ctx, seed=9)
+    th = np.zeros(ditr.GNN_PARAMS, np.float32)
+    th[-1] = 2.0  # z = b3 everywhere
+    net.set_params(th)
+    b = np.zeros(case["n"])
+    b[123] = 0.15
+    info, l1 = check_start(case, net, b)
+    assert int(np.argmin(l1)) == 0 and info.fell_back == 1 and info.scale_c == 0.0
+    net.close()
+
+
+def test_training_reduces_loss(ctx):
+    dev = torch.device("cuda", 0)
+    data = []
+    for s in range(1100, 1104):
+        cp, ri = ditgen.generate(ditgen.GraphSpec(n=20_000, block=1000, seed=s))
+        keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+        g = ditr.Graph(ctx, *keep)
+        b = torch.full((cp.size - 1,), 0.15 / (cp.size - 1), dtype=torch.float64, device=dev)
+        h = torch.empty_like(b)
+        f = torch.empty(cp.size - 1, dtype=torch.float32, device=dev)
+        ditr.solve(ctx, g, b, h, f, rel_tol=1e-10, allow=(ditr.OK,))
+        y, w = ditr.gnn_targets(ctx, g, h, 0.15)
+        data.append((keep, g, y, w))
+    net = ditr.Gnn(ctx, seed=7)
+    first = np.mean([net.grad(g, y, w)[0] for _, g, y, w in data])
+    for ep in range(15):
+        for _, g, y, w in data:
+            net.train_step(g, y, w, lr=3e-3, want_loss=False)
+    last = np.mean([net.grad(g, y, w)[0] for _, g, y, w in data])
+    assert np.isfinite(last) and last < 0.5 * first
+    net.close()
+
+
+def test_learned_start_saves_diffusions(ctx):
+    """Trained on 16 generated graphs of 1e5 nodes, the network's start on two
+    unseen 2e5-node graphs reaches the same tolerance with fewer diffused edges
+    than H_0 = 0, and both results keep parity with the oracle."""
+    dev = torch.device("cuda", 0)
+    train = []
+    for s in range(1000, 1016):
+        cp, ri = ditgen.generate(ditgen.GraphSpec(n=100_000, block=1000, seed=s))
+        keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+        g = ditr.Graph(ctx, *keep)
+        b = torch.full((cp.size - 1,), 0.15 / (cp.size - 1), dtype=torch.float64, device=dev)
+        h = torch.empty_like(b)
+        f = torch.empty(cp.size - 1, dtype=torch.float32, device=dev)
+        ditr.solve(ctx, g, b, h, f, rel_tol=1e-10, allow=(ditr.OK,))
+        y, w = ditr.gnn_targets(ctx, g, h, 0.15)
+        train.append((keep, g, y, w))
+    net = ditr.Gnn(ctx, block=1000, seed=7)
+    for ep in range(20):
+        lr = 3e-3 if ep < 14 else 1e-3
+        for _, g, y, w in train:
+            net.train_step(g, y, w, lr=lr, want_loss=False)
+    for s in (2000, 2001):
+        cp, ri = ditgen.generate(ditgen.GraphSpec(n=200_000, block=1000, seed=s))
+        n = cp.size - 1
+        keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+        g = ditr.Graph(ctx, *keep)
+        b = ditgen.uniform_b(n)
+        bt = torch.from_numpy(b).to(dev)
+        h = torch.empty(n, dtype=torch.float64, device=dev)
+        f = torch.empty(n, dtype=torch.float32, device=dev)
+        cold = ditr.solve(ctx, g, bt, h, f, rel_tol=1e-9, allow=(ditr.OK,))
+        h_cold = h.cpu().numpy()
+        info = net.predict_h0(g, bt, h, f)
+        warm = ditr.solve(ctx, g, bt, h, f, warm=True, rel_tol=1e-9, allow=(ditr.OK,))
+        h_warm = h.cpu().numpy()
+        print("graph %d: cold %.3e edges, warm %.3e edges (start fluid %.3f of B, c = %.2f)"
+              % (s, cold.edges, warm.edges, info.f0_l1 / info.b_l1, info.scale_c))
+        assert info.fell_back == 0 and info.f0_l1 < 0.8 * info.b_l1
+        assert warm.edges < 0.9 * cold.edges
+        ref = oracle.solve(cp, ri, b, rel_tol=1e-12)
+        for hh, st in ((h_cold, cold), (h_warm, warm)):
+            err = np.abs(hh - ref.h).sum()
+            assert err <= (st.resid_l1 + ref.resid_l1) / (1 - D) * (1 + 1e-6)
+            assert err <= 1e-6 * ref.h.sum()
+        g.close()
+
+
+def test_handles_outlive_their_context():
+    """Graphs and networks destroyed after their context (C level), and the
+    binding closing them before the context."""
+    dev = torch.device("cuda", 0)
+    cp, ri = ditgen.generate(ditgen.GraphSpec(n=5_000, block=100, seed=4))
+    keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+    c2 = ditr.Context(0)
+    g, net = ditr.Graph(c2, *keep), ditr.Gnn(c2, seed=1)
+    net.forward(g)
+    ditr.lib().ditr_destroy(c2.handle)
+    c2.handle = None
+    assert ditr.lib().ditr_graph_destroy(g.handle) == ditr.OK
+    assert ditr.lib().ditr_gnn_destroy(net.handle) == ditr.OK
+    g.handle = net.handle = None
+    c3 = ditr.Context(0)
+    g3, n3 = ditr.Graph(c3, *keep), ditr.Gnn(c3, seed=1)
+    c3.close()
+    assert g3.handle is None and n3.handle is None
