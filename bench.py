@@ -7,7 +7,15 @@ the exact residual refreshes and the final check. Graph upload and the
 partition plan are built once before the timed region (reported apart).
 
 Prints one JSON line. `value` is diffused edges per second over the timed
-steps; `time_to_tol_ms` is the wall time of one solve.
+steps; `time_to_tol_ms` is the wall time of one solve. Two comparisons at the
+same accuracy ride along (not part of `value`):
+  batched      256 personalized right-hand sides (seed sets of 1..1000 nodes,
+               log-uniform, mass 0.15) to 1e-8 ||B_r||_1 each in one batched
+               solve, against plain solves of a sample of the same columns;
+  warm_start   the network trained on 64 generated graphs of 1e5 nodes (seeds
+               1000..1063, untimed), then on 8 unseen 1e6-node graphs (seeds
+               2000..2007): prediction + exact start fluid + diffusion against a
+               cold start, both to 1e-9 ||B||_1.
 """
 import argparse
 import json
@@ -46,6 +54,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="DITR_MODE_* (0 = default)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -85,6 +95,150 @@ def cpu_baseline(cp, ri, b, tol):
         "kind": "oracle",
         "sample": "full 1e6-node solve to 1e-9 ||B||_1, best of %d runs: %.3f s, %.3e edges"
                   % (len(runs), best.seconds, best.edges),
+    }
+
+
+def batched_bench(ctx, g, n, dev):
+    """256 personalized right-hand sides in one batched solve vs plain solves."""
+    import numpy as np
+    import torch
+
+    import ditgen
+    from paper_1202_6168_amd import ditr
+
+    R, tol = 256, 1e-8
+    sets = ditgen.ppr_seed_sets(n, R, seed=42)
+    B = torch.from_numpy(ditgen.ppr_rhs_dense(n, sets)).to(dev)
+    H = torch.empty_like(B)
+    F = torch.empty((n, R), dtype=torch.float32, device=dev)
+    ditr.solve_batched(ctx, g, B, H, F, rel_tol=tol, allow=(ditr.OK,))  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot, per = ditr.solve_batched(ctx, g, B, H, F, rel_tol=tol, allow=(ditr.OK,))
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    worst = max(p.resid_l1 / p.b_l1 for p in per)
+    del H, F
+    # plain solves of an evenly spaced sample of the columns
+    cols = list(range(0, R, R // 16))
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    h = torch.empty(n, dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float32, device=dev)
+    t_plain, e_plain = [], []
+    for r in cols:
+        b.copy_(B[:, r])
+        ditr.solve(ctx, g, b, h, f, rel_tol=tol, allow=(ditr.OK,))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ditr.solve(ctx, g, b, h, f, rel_tol=tol, allow=(ditr.OK,))
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+        e_plain.append(st.edges)
+    del B
+    per_rhs = t_batch / R
+    plain = float(np.mean(t_plain))
+    return {
+        "rhs": R,
+        "tol": tol,
+        "batched_ms": 1e3 * t_batch,
+        "batched_ms_per_rhs": 1e3 * per_rhs,
+        "plain_ms_per_rhs": 1e3 * plain,
+        "plain_sample": "%d evenly spaced columns, each solved alone" % len(cols),
+        "speedup_per_rhs": plain / per_rhs,
+        "batched_lane_edges": tot.edges,
+        "batched_lane_edges_per_s": tot.edges / t_batch,
+        "plain_edges_per_rhs": float(np.mean(e_plain)),
+        "batched_edges_per_rhs": tot.edges / R,
+        "worst_resid_rel": worst,
+        "rounds": tot.rounds,
+    }
+
+
+def warm_bench(ctx, dev):
+    """Train the warm-start network, then cold vs learned start on unseen graphs."""
+    import numpy as np
+    import torch
+
+    import ditgen
+    from paper_1202_6168_amd import ditr
+
+    t0 = time.perf_counter()
+    train = []
+    for s in range(1000, 1064):
+        cp, ri = ditgen.generate(ditgen.GraphSpec(n=100_000, block=1000, seed=s))
+        keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+        g = ditr.Graph(ctx, *keep)
+        n = cp.size - 1
+        b = torch.full((n,), 0.15 / n, dtype=torch.float64, device=dev)
+        h = torch.empty_like(b)
+        f = torch.empty(n, dtype=torch.float32, device=dev)
+        ditr.solve(ctx, g, b, h, f, rel_tol=1e-10, allow=(ditr.OK,))
+        y, w = ditr.gnn_targets(ctx, g, h, 0.15)
+        train.append((keep, g, y, w))
+    t_labels = time.perf_counter() - t0
+    net = ditr.Gnn(ctx, block=1000, seed=7)
+    epochs = 40
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        lr = 3e-3 if ep < 2 * epochs // 3 else 1e-3
+        for _, g, y, w in train:
+            net.train_step(g, y, w, lr=lr, want_loss=False)
+    loss = float(np.mean([net.grad(g, y, w)[0] for _, g, y, w in train]))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for _, g, _, _ in train:
+        g.close()
+    del train
+
+    rows = []
+    for s in range(2000, 2008):
+        cp, ri = ditgen.generate(ditgen.GraphSpec(n=1_000_000, block=1000, seed=s))
+        n = cp.size - 1
+        keep = (torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+        g = ditr.Graph(ctx, *keep)
+        bt = torch.from_numpy(ditgen.uniform_b(n)).to(dev)
+        h = torch.empty(n, dtype=torch.float64, device=dev)
+        f = torch.empty(n, dtype=torch.float32, device=dev)
+        best_c, best_w = None, None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cold = ditr.solve(ctx, g, bt, h, f, rel_tol=1e-9, allow=(ditr.OK,))
+            torch.cuda.synchronize()
+            tc = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            info = net.predict_h0(g, bt, h, f)
+            t1 = time.perf_counter()
+            warm = ditr.solve(ctx, g, bt, h, f, warm=True, rel_tol=1e-9, allow=(ditr.OK,))
+            torch.cuda.synchronize()
+            tw, tp = time.perf_counter() - t0, t1 - t0
+            if best_c is None or tc < best_c[0]:
+                best_c = (tc, cold)
+            if best_w is None or tw < best_w[0]:
+                best_w = (tw, warm, tp, info)
+        row = {"graph_seed": s, "cold_ms": 1e3 * best_c[0], "cold_edges": best_c[1].edges,
+               "warm_ms": 1e3 * best_w[0], "predict_ms": 1e3 * best_w[2],
+               "warm_edges": best_w[1].edges, "start_fluid_rel": best_w[3].f0_l1 / best_w[3].b_l1,
+               "scale_c": best_w[3].scale_c, "fell_back": int(best_w[3].fell_back)}
+        if s == 2000:  # parity of the warm result against the FP64 oracle
+            import oracle
+
+            ref = oracle.solve(cp, ri, ditgen.uniform_b(n), rel_tol=1e-12)
+            row["warm_err_rel_vs_oracle"] = float(np.abs(h.cpu().numpy() - ref.h).sum() / ref.h.sum())
+        rows.append(row)
+        g.close()
+    ce = sum(r["cold_edges"] for r in rows)
+    we = sum(r["warm_edges"] for r in rows)
+    return {
+        "train": "64 graphs of 1e5 nodes, %d epochs, Adam; labels %.1f s, training %.1f s, final loss %.4f"
+                 % (epochs, t_labels, t_train, loss),
+        "tol": 1e-9,
+        "edges_saved_frac": 1 - we / ce,
+        "cold_ms_mean": float(np.mean([r["cold_ms"] for r in rows])),
+        "warm_ms_mean": float(np.mean([r["warm_ms"] for r in rows])),
+        "predict_ms_mean": float(np.mean([r["predict_ms"] for r in rows])),
+        "graphs": rows,
     }
 
 
@@ -185,10 +339,14 @@ def main():
             "launches": klaunch,
         },
     }
+    if not args.no_batched:
+        out["batched"] = batched_bench(ctx, g, spec.n, dev)
+    g.close()
+    if not args.no_warm:
+        out["warm_start"] = warm_bench(ctx, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cp, ri, b, args.tol)
     print(json.dumps(out))
-    g.close()
     ctx.close()
 
 
