@@ -68,9 +68,10 @@ enum { DITR_MODE_AUTO = 0,       /* = DITR_MODE_PARTITION */
                                     (Sections 2.3-2.6, asynchronous) */
        DITR_MODE_SWEEP = 2,      /* one grid-wide threshold sweep per launch, pulled over the
                                     transpose (Section 2.4 applied to a node set) */
-       DITR_MODE_PARTITION = 3   /* one launch = m local threshold sweeps per partition in LDS,
-                                    outside fluid pulled as p_ji times the H increment
-                                    (Sections 2.3-2.5, synchronous exchange) */ };
+       DITR_MODE_PARTITION = 3   /* per threshold level, m local threshold sweeps per partition
+                                    in LDS, outside fluid pulled as p_ji times the H increment
+                                    (Sections 2.3-2.5, synchronous exchange); partitions stay
+                                    resident across levels when they all fit the device */ };
 
 typedef struct {
   double alpha;        /* threshold divisor after each sweep (Section 2.4); > 1; default 1.5 */
@@ -96,6 +97,10 @@ typedef struct {
 /* opts.flags: time every diffusion launch with HIP events on the context's
  * stream and report the sum in ditr_stats.kernel_seconds. */
 #define DITR_FLAG_TIME_KERNELS 1u
+/* opts.flags: in DITR_MODE_PARTITION, relaunch the sweep once per threshold
+ * level even when every partition could stay resident in one cooperative
+ * launch (the default whenever the partitions fit the device at once). */
+#define DITR_FLAG_NO_RESIDENT 2u
 
 typedef struct {
   int64_t edges;       /* elementary edge diffusions (Section 2.4: normalized iterations x L) */

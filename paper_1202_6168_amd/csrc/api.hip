@@ -274,9 +274,9 @@ int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
     return rc;
   }
   // a partition's nodes must fit the LDS of both partitioned kernels
-  // (12 bytes per node for the asynchronous one, 20 for the partitioned sweep)
+  // (12 bytes per node for the asynchronous one, 22 for the partitioned sweep)
   const int64_t cap_nodes = std::min<int64_t>(
-      65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 20)));
+      65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 22)));
   int64_t K;
   if (o.part_nodes > 0) {
     K = (n + o.part_nodes - 1) / o.part_nodes;
@@ -478,13 +478,39 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     rc = launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
     if (mode == DITR_MODE_PARTITION) {
-      // launches of m local sweeps in batches; the stop flag turns the rest of a batch into no-ops
       rc = launch_part_prepare(c, g);
       if (rc) return finish(rc);
       const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
       const int batch = kBatch;
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
-      for (int64_t done_l = 0; done_l < budget; done_l += batch) {
+      bool resident = false;
+      if (!(o.flags & DITR_FLAG_NO_RESIDENT)) {
+        rc = part_resident_fits(c, g, &resident);
+        if (rc) return finish(rc);
+      }
+      if (resident) {
+        // every partition resident for the whole stage: one cooperative launch
+        const uint64_t before = c->ctrl_host->sweeps;
+        rc = t_begin();
+        if (!rc) {
+          rc = launch_part_resident(c, g, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30));
+          if (rc == DITR_EHIP) {  // cooperative launch refused: relaunch per level instead
+            (void)hipGetLastError();
+            resident = false;
+            rc = DITR_OK;
+          }
+        }
+        if (!rc && resident) rc = t_end(0);
+        if (!rc && resident) rc = read_ctrl(c);
+        if (rc) return finish(rc);
+        if (resident && c->ctrl_host->err == 2)
+          return finish(set_error(DITR_EHIP, "a grid barrier of the resident sweep timed out"));
+        if (resident && timed) st.timed_launches += (int64_t)(c->ctrl_host->sweeps - before);
+        if (resident) st.launches += 1;
+      }
+      // otherwise launches of m local sweeps in batches; the stop flag turns the
+      // rest of a batch into no-ops
+      for (int64_t done_l = 0; !resident && done_l < budget; done_l += batch) {
         const uint64_t before = c->ctrl_host->sweeps;
         rc = launch_part_sweeps(c, g, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr);
         if (!rc) rc = read_ctrl(c);

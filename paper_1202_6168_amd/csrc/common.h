@@ -49,6 +49,7 @@ struct PartPlan {
   int32_t* pid = nullptr;        // [n] partition of each node
   int32_t* loc_ptr = nullptr;    // [n+1] local CSC: out-links that stay in the partition
   uint16_t* loc_idx = nullptr;   //   target - partition start
+  uint16_t* order = nullptr;     // [n] visiting order inside each partition (falling local degree)
   float* pw = nullptr;           // [n] d / #out_i (0 for a dangling node)
   int32_t* ext_deg = nullptr;    // [n] out-links leaving the partition
   int32_t* ext_ptr = nullptr;    // [K+1] external in-links of each partition (light rows)
@@ -57,12 +58,20 @@ struct PartPlan {
   int32_t* heavy_rows = nullptr; // rows with more than kPartHeavy external in-links, ascending
   int32_t* part_heavy = nullptr; // [K+1] range of heavy_rows inside each partition
   int32_t* heavy_src = nullptr;  // external in-links of heavy rows (CSR order)
-  int32_t* heavy_edge_row = nullptr;  // heavy link -> index into heavy_rows
+  int32_t* item_row = nullptr;   // heavy items (kItem links of one heavy row): local row
+  int32_t* item_beg = nullptr;   //   links [item_beg, item_end) of heavy_src
+  int32_t* item_end = nullptr;
+  int32_t* part_items = nullptr; // [K+1] items of each partition
+  double* item_sum = nullptr;    // [n_items] item inflow
+  int* item_flag = nullptr;      // [n_items] epoch of the stored sum (resident sweep)
+  int32_t* short_items = nullptr; // items of at most 64 links
+  int32_t* long_items = nullptr;  // longer items
+  int32_t n_items = 0, n_short = 0, n_long = 0;
+  int64_t epoch = 0;             // epochs handed out to resident launches so far
   float* S = nullptr;            // [2][n] published p_i dH_i
-  double* heavy_in = nullptr;    // [n_heavy] inflow of heavy rows in the current launch
-  int* counters = nullptr;       // [2] finished workgroups at [1]
-  double* partials = nullptr;    // [K + chunks][4]
-  int32_t n_heavy = 0, n_chunks = 0;
+  int* counters = nullptr;       // [8] finished workgroups at [1], grid barrier at [2..4]
+  double* partials = nullptr;    // [2][K][4] per-workgroup sums
+  int32_t n_heavy = 0;
   int32_t max_local_edges = 0;   // most local out-links in one partition
   int64_t n_local = 0, n_ext = 0, n_heavy_edges = 0;
 };
@@ -98,7 +107,7 @@ struct ditr_graph {
 
 constexpr int kHeavyRow = 64;     // in-degree above which a row's in-links are split in chunks
 constexpr int kHeavyChunk = 2048; // in-links per chunk workgroup
-constexpr int kPartHeavy = 4;     // external in-links above which a row's inflow is summed apart
+constexpr int kPartHeavy = 8;     // external in-links above which a row's inflow is summed in items
 
 // ---- error reporting (api.hip) ------------------------------------------
 int set_error(int code, const char* fmt, ...);
@@ -136,6 +145,12 @@ __device__ __forceinline__ int ld_agent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int ld_system(const int* p) {
@@ -226,6 +241,9 @@ size_t part_lds_bytes(int nodes, int local_edges);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
                        int nlaunch, hipEvent_t* ev);
+int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits);
+int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
+                         int max_levels);
 struct PersistentCfg {
   int block;
   int grid;

@@ -26,6 +26,8 @@ namespace {
 
 constexpr int kPB = 1024;     // threads per partition workgroup
 constexpr int kStride = 4;    // doubles per block in the partials
+constexpr int kCounters = 8;  // launch finish count, grid barrier, stop vote
+constexpr int kItem = 512;    // links of a heavy row summed by one wave (8 per lane)
 
 int grid_for(int64_t n, int block, int cap) {
   int64_t g = (n + block - 1) / block;
@@ -130,13 +132,6 @@ __global__ void k_gather_ptr(int K, const int32_t* __restrict__ part_ptr,
     out[k] = row_scan[part_ptr[k]];
 }
 
-__global__ void k_heavy_edge_rows(int32_t nh, const int32_t* __restrict__ rows,
-                                  const int32_t* __restrict__ heavy_ptr, int32_t* hre) {
-  for (int32_t h = blockIdx.x; h < nh; h += gridDim.x)
-    for (int32_t e = heavy_ptr[rows[h]] + threadIdx.x; e < heavy_ptr[rows[h] + 1]; e += blockDim.x)
-      hre[e] = h;
-}
-
 __global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy_ptr, int32_t* list,
                              int* count) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -158,97 +153,321 @@ __global__ void k_weights(int64_t n, const int32_t* __restrict__ col_ptr,
 struct PartArgs {
   int64_t n;
   int K;
-  int m;  // local sweeps per launch
+  int m;  // local sweeps per threshold level
   const int32_t* __restrict__ part_ptr;
   const int32_t* __restrict__ col_ptr;
   const int32_t* __restrict__ loc_ptr;
   const uint16_t* __restrict__ loc_idx;
+  const uint16_t* __restrict__ order;  // [n] visiting order inside each partition (local ids)
   const float* __restrict__ pw;
   const int32_t* __restrict__ ext_deg;
   const int32_t* __restrict__ ext_ptr;   // [K+1] light external in-links of each partition
   const int32_t* __restrict__ ext_src;
   const uint16_t* __restrict__ ext_row;
-  const int32_t* __restrict__ heavy_rows;
-  const int32_t* __restrict__ part_heavy;  // [K+1] heavy rows of each partition (ranges of heavy_rows)
-  const int32_t* __restrict__ heavy_src;
-  const int32_t* __restrict__ heavy_edge_row;  // heavy link -> index into heavy_rows
-  int64_t n_heavy_edges;
+  const int32_t* __restrict__ heavy_src;   // external in-links of the heavy rows, row by row
+  const int32_t* __restrict__ part_items;  // [K+1] heavy items of each partition
+  const int32_t* __restrict__ item_row;    // item -> row - partition start
+  const int32_t* __restrict__ item_beg;    // item -> its links [item_beg, item_end) of heavy_src
+  const int32_t* __restrict__ item_end;
+  double* item_sum;  // [n_items] inflow of one item
+  int* item_flag;    // [n_items] epoch of the level whose item_sum is stored (resident)
+  const int32_t* __restrict__ short_items;  // items of at most 64 links (8 lanes each)
+  const int32_t* __restrict__ long_items;   // longer items (a wave each)
+  int n_items, n_short, n_long;
+  int epoch0;        // resident: epoch of level 0 (grows across launches)
   float* F;
   double* H;
   float* S;          // [2][n] published p_i dH_i
-  double* heavy_in;  // [n_heavy] inflow of heavy rows in the current launch
-  double* partials;
-  int* counters;     // [1] finished workgroups (reset by the last)
-  int n_chunks;
+  double* partials;  // [2][K][kStride] per-workgroup sums (resident: by level parity)
+  int* counters;     // [1] finished workgroups (launches); [2], [3] grid barrier; [4] stop vote
   Ctrl* ctrl;
+  const int* abort_flag;  // host abort word (mapped)
   int n_heavy;
   int lds_nodes;   // node capacity of the LDS layout
   int lds_edges;   // local-target capacity (a larger partition reads its targets from memory)
+  int max_levels;  // resident kernel: threshold levels before it returns
   float alpha;
   float d;
   double dd;  // damping in FP64 for the published shares
 };
 
-// lane owning edge slot e: first lane whose inclusive prefix exceeds e
-__device__ __forceinline__ int owner_of(int incl, int e) {
-  int k = 0;
-#pragma unroll
-  for (int s = 32; s > 0; s >>= 1) {
-    int v = __shfl(incl, k + s - 1, 64);
-    if (v <= e) k += s;
-  }
-  return k;
+// A partition's view of the dynamic LDS: history increment (FP64), fluid
+// (FP32), local CSC offsets, out-degrees, visiting order and, when they fit,
+// the local targets.
+struct PartView {
+  double* dH;
+  float* Fl;
+  int32_t* lptr;
+  int32_t* odeg;
+  uint16_t* ord;
+  uint32_t* lidx_words;
+  const uint16_t* lidx;
+  int lo, np, lbase, nl;
+  bool lidx_in_lds;
+};
+
+__device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* smem, int p) {
+  PartView v;
+  const int cap = a.lds_nodes;
+  v.dH = reinterpret_cast<double*>(smem);
+  v.Fl = reinterpret_cast<float*>(smem + (size_t)cap * 8);
+  v.lptr = reinterpret_cast<int32_t*>(smem + (size_t)cap * 12);
+  v.odeg = reinterpret_cast<int32_t*>(smem + (size_t)cap * 16 + 4);
+  v.ord = reinterpret_cast<uint16_t*>(smem + (size_t)cap * 20 + 4);
+  v.lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4 + (((size_t)cap * 2 + 3) & ~(size_t)3));
+  v.lo = a.part_ptr[p];
+  v.np = a.part_ptr[p + 1] - v.lo;
+  v.lbase = a.loc_ptr[v.lo];
+  v.nl = a.loc_ptr[v.lo + v.np] - v.lbase;
+  v.lidx_in_lds = v.nl + 2 <= a.lds_edges;
+  // the LDS copy keeps the parity of lbase so that it moves whole 32-bit words
+  v.lidx = v.lidx_in_lds ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1)
+                         : a.loc_idx + v.lbase;
+  return v;
 }
 
-// Inflow of the heavy rows, summed right before the partition launch that
-// consumes it. The external in-links of all heavy rows form one list in row
-// order; workgroup c sums the range [c kHeavyChunk, (c+1) kHeavyChunk) of it:
-// each thread reduces a run of consecutive links per row, the runs meet in
-// FP64 LDS slots (one per row of the range), and each slot goes to heavy_in
-// with one device atomic. The partition owning the row clears it after use.
-__global__ void __launch_bounds__(256) k_part_heavy(PartArgs a, int parity) {
-  if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
-  __shared__ double acc[kHeavyChunk];
+// 1. load the partition into LDS (several loads in flight per thread)
+template <int BLOCK>
+__device__ void part_load(const PartArgs& a, const PartView& v) {
   const int tid = threadIdx.x;
-  const int64_t beg = (int64_t)blockIdx.x * kHeavyChunk;
-  const int64_t end = beg + kHeavyChunk < a.n_heavy_edges ? beg + kHeavyChunk : a.n_heavy_edges;
-  const int h0 = a.heavy_edge_row[beg];
-  const int nslot = a.heavy_edge_row[end - 1] - h0 + 1;
-  for (int k = tid; k < nslot; k += 256) acc[k] = 0.0;
-  __syncthreads();
-  constexpr int R = kHeavyChunk / 256;  // consecutive links per thread
-  const int64_t e0 = beg + (int64_t)tid * R;
-  int hk[R];
-  float v[R];
+  {
+    constexpr int U = 4;
+    for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
+      float f[U];
+      int32_t lp[U], c0[U], c1[U];
 #pragma unroll
-  for (int k = 0; k < R; ++k) {  // all loads first
-    const int64_t e = e0 + k;
-    hk[k] = e < end ? a.heavy_edge_row[e] : -1;
-    v[k] = e < end ? S_in[a.heavy_src[e]] : 0.f;
-  }
-  double run = 0;
-  int hr = hk[0];
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * BLOCK;
+        if (i < v.np) {
+          f[u] = a.F[v.lo + i];
+          lp[u] = a.loc_ptr[v.lo + i];
+          c0[u] = a.col_ptr[v.lo + i];
+          c1[u] = a.col_ptr[v.lo + i + 1];
+        }
+      }
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (hk[k] < 0) break;
-    if (hk[k] != hr) {
-      if (run != 0.0) atomicAdd(&acc[hr - h0], run);  // ds_add_f64
-      run = 0;
-      hr = hk[k];
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * BLOCK;
+        if (i < v.np) {
+          v.Fl[i] = f[u];
+          v.dH[i] = 0.0;
+          v.lptr[i] = lp[u] - v.lbase;
+          v.odeg[i] = c1[u] - c0[u];
+        }
+      }
     }
-    run += (double)v[k];
   }
-  if (hr >= 0 && run != 0.0) atomicAdd(&acc[hr - h0], run);
+  if (tid == 0) v.lptr[v.np] = v.nl;
+  for (int i = tid; i < v.np; i += BLOCK) v.ord[i] = a.order[v.lo + i];
+  if (v.lidx_in_lds) {
+    constexpr int U = 8;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.loc_idx) + (v.lbase >> 1);
+    const int words = ((v.lbase & 1) + v.nl + 1) >> 1;
+    for (int w0 = tid; w0 < words; w0 += U * BLOCK) {
+      uint32_t x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (w0 + u * BLOCK < words) x[u] = src[w0 + u * BLOCK];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (w0 + u * BLOCK < words) v.lidx_words[w0 + u * BLOCK] = x[u];
+    }
+  }
   __syncthreads();
-  for (int k = tid; k < nslot; k += 256)
-    if (acc[k] != 0.0) add_agent(&a.heavy_in[h0 + k], acc[k]);
+}
+
+// Sums of heavy items: rows with more than kPartHeavy external in-links are cut
+// in items of at most kItem links. Eight lanes sum a short item (at most 64
+// links, 8 per lane), a whole wave a long one; every lane has its gathers in
+// flight together. The sum is stored, then, when resident, the item's epoch
+// flag. The work units (8 short items, or one long item) are spread
+// round-robin over all waves of the grid, so a hub's inflow is summed by many
+// workgroups at once.
+template <bool RESIDENT>
+__device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first_wave, int64_t n_waves,
+                          int epoch) {
+  const int lane = threadIdx.x & 63;
+  auto S = [&](int32_t i) { return RESIDENT ? ld_agent(&S_in[i]) : S_in[i]; };
+  auto store = [&](int64_t k, double x) {
+    if (RESIDENT) {
+      st_agent(&a.item_sum[k], x);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // the sum lands before the flag
+      st_agent(&a.item_flag[k], epoch);
+    } else {
+      a.item_sum[k] = x;
+    }
+  };
+  const int64_t w_short = (a.n_short + 7) / 8;
+  for (int64_t w = first_wave; w < w_short + a.n_long; w += n_waves) {
+    if (w < w_short) {
+      const int64_t j = w * 8 + (lane >> 3);
+      const bool on = j < a.n_short;
+      const int64_t k = on ? a.short_items[j] : 0;
+      double x = 0;
+      if (on) {
+        const int32_t e0 = a.item_beg[k] + (lane & 7), e1 = a.item_end[k];
+        int32_t src[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) src[q] = e0 + 8 * q < e1 ? a.heavy_src[e0 + 8 * q] : -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (src[q] >= 0) x += (double)S(src[q]);
+      }
+      x += __shfl_xor(x, 1, 64);
+      x += __shfl_xor(x, 2, 64);
+      x += __shfl_xor(x, 4, 64);
+      if (on && (lane & 7) == 0) store(k, x);
+    } else {
+      const int64_t k = a.long_items[w - w_short];
+      const int32_t e0 = a.item_beg[k] + lane, e1 = a.item_end[k];
+      int32_t src[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) src[q] = e0 + 64 * q < e1 ? a.heavy_src[e0 + 64 * q] : -1;
+      double x = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (src[q] >= 0) x += (double)S(src[q]);
+      x = wave_sum(x);
+      if (lane == 0) store(k, x);
+    }
+  }
+}
+
+// 2. outside fluid, pulled by the partition that owns it: each light external
+// in-link (source, local row) adds the source's published share (one thread
+// per link, LDS atomics); each heavy item of the partition adds its sum
+// (resident: once its flag shows this level's epoch; a wait longer than
+// spin_limit polls sets ctrl->err = 2 and ends the wait). RESIDENT: the values
+// were published inside the same kernel, so they are read at agent scope.
+// Returns false on a timed-out wait.
+template <int BLOCK, bool RESIDENT>
+__device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const float* S_in, int epoch,
+                            int spin_limit) {
+  const int tid = threadIdx.x;
+  auto ld = [&](int32_t s) { return RESIDENT ? ld_agent(&S_in[s]) : S_in[s]; };
+  const int e0 = a.ext_ptr[p], e1 = a.ext_ptr[p + 1];
+  int e = e0 + tid;
+  for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {  // four gathers in flight
+    const int32_t s0 = a.ext_src[e], s1 = a.ext_src[e + BLOCK], s2 = a.ext_src[e + 2 * BLOCK],
+                  s3 = a.ext_src[e + 3 * BLOCK];
+    const uint16_t r0 = a.ext_row[e], r1 = a.ext_row[e + BLOCK], r2 = a.ext_row[e + 2 * BLOCK],
+                   r3 = a.ext_row[e + 3 * BLOCK];
+    const float v0 = ld(s0), v1 = ld(s1), v2 = ld(s2), v3 = ld(s3);
+    if (v0 != 0.f) atomicAdd(&v.Fl[r0], v0);
+    if (v1 != 0.f) atomicAdd(&v.Fl[r1], v1);
+    if (v2 != 0.f) atomicAdd(&v.Fl[r2], v2);
+    if (v3 != 0.f) atomicAdd(&v.Fl[r3], v3);
+  }
+  for (; e < e1; e += BLOCK) {
+    const float x = ld(a.ext_src[e]);
+    if (x != 0.f) atomicAdd(&v.Fl[a.ext_row[e]], x);
+  }
+  bool ok = true;
+  for (int k = a.part_items[p] + tid; k < a.part_items[p + 1]; k += BLOCK) {
+    if (RESIDENT) {
+      int spins = 0;
+      while (ld_agent(&a.item_flag[k]) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > spin_limit) {
+          ok = false;
+          __hip_atomic_store(&a.ctrl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      if (!ok) break;
+    }
+    const double x = RESIDENT ? ld_agent(&a.item_sum[k]) : a.item_sum[k];
+    if (x != 0.0) atomicAdd(&v.Fl[a.item_row[k]], (float)x);
+  }
+  return __syncthreads_and(ok) != 0;
+}
+
+// 3. local threshold sweeps at one T until none passes (at most m). Each
+// thread takes one node of the visiting order at a time (consecutive slots
+// hold nodes of about the same local out-degree, so a wave's lanes finish
+// their lists together) and pushes its share to every local target with LDS
+// atomics, eight targets per step: their loads are issued together, then the
+// adds. TARGETS_LDS: the local targets were copied to LDS (the pointer then has
+// a known address space and the loop waits on LDS traffic only).
+template <int BLOCK, bool TARGETS_LDS>
+__device__ void part_sweeps_t(const PartArgs& a, const PartView& v, float T, double& edges,
+                              double& diffs) {
+  const uint16_t* __restrict__ lidx =
+      TARGETS_LDS ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1) : a.loc_idx + v.lbase;
+  const float d = a.d;
+  for (int s = 0; s < a.m; ++s) {
+    int passed = 0;
+    for (int k = threadIdx.x; k < v.np; k += BLOCK) {
+      const int i = v.ord[k];
+      if (!(fabsf(v.Fl[i]) > T)) continue;
+      const float sent = atomicExch(&v.Fl[i], 0.f);
+      v.dH[i] += (double)sent;
+      const int od = v.odeg[i];
+      // FP32 share of the in-LDS fluid; the published shares and the exact
+      // residual use d / #out_i in FP64
+      const float w = od > 0 ? sent * d * __builtin_amdgcn_rcpf((float)od) : 0.f;
+      edges += (double)od;
+      diffs += 1.0;
+      passed = 1;
+      const int e1 = v.lptr[i + 1];
+      for (int e = v.lptr[i]; e < e1; e += 8) {
+        int t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = e + q < e1 ? (int)lidx[e + q] : -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (t[q] >= 0) atomicAdd(&v.Fl[t[q]], w);  // ds_add_f32
+      }
+    }
+    if (!__syncthreads_or(passed)) break;  // barrier + "did any node pass"
+  }
+}
+
+template <int BLOCK>
+__device__ void part_sweeps(const PartArgs& a, const PartView& v, float T, double& edges,
+                            double& diffs) {
+  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, T, edges, diffs);
+  else part_sweeps_t<BLOCK, false>(a, v, T, edges, diffs);
+}
+
+// block-wide sums of (resid, edges, diffs) and max of fmx, in a fixed order;
+// the result is valid in every thread
+template <int BLOCK>
+__device__ void block_reduce4(double& r0, double& r1, double& r2, double& r3, double (*red)[BLOCK / 64]) {
+  constexpr int NW = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  r0 = wave_sum(r0);
+  r1 = wave_maxd(r1);
+  r2 = wave_sum(r2);
+  r3 = wave_sum(r3);
+  __syncthreads();  // red may still be read by an earlier reduction
+  if (lane == 0) {
+    red[0][wave] = r0;
+    red[1][wave] = r1;
+    red[2][wave] = r2;
+    red[3][wave] = r3;
+  }
+  __syncthreads();
+  r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+  for (int w = 0; w < NW; ++w) {
+    r0 += red[0][w];
+    r1 = fmax(r1, red[1][w]);
+    r2 += red[2][w];
+    r3 += red[3][w];
+  }
+}
+
+// Heavy-item sums as their own kernel, right before a launch of the sweep.
+__global__ void __launch_bounds__(256) k_part_items(PartArgs a, int parity) {
+  if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  item_sums<false>(a, a.S + (size_t)(parity ^ 1) * a.n, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6),
+                   (int64_t)gridDim.x * 4, 0);
 }
 
 // One launch of the partitioned sweep. Workgroup p:
 //   1. loads Omega_p into LDS (fluid, history increment, local CSC);
-//   2. adds the outside fluid: heavy rows take what k_part_heavy summed for
-//      them, light rows pull S_in over their external in-links;
+//   2. pulls the outside fluid S_in over its light external in-links and adds
+//      the sums of its heavy items (k_part_items, just before);
 //   3. runs up to m threshold sweeps at the launch's T until none passes;
 //   4. writes F and H back and publishes S_out = p_i dH_i;
 //   5. the last workgroup to finish reduces the per-workgroup sums and sets
@@ -258,186 +477,48 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
   float* S_out = a.S + (size_t)parity * a.n;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   constexpr int NW = BLOCK / 64;
   __shared__ double red[4][NW];
-  __shared__ uint8_t s_mark[NW][2][64];  // per-wave scratch of the edge expansion
-  __shared__ int s_off[NW][64];
-  __shared__ float s_w[NW][64];
   __shared__ int s_last;
-
-  // LDS: fluid, history increment, local CSC (offsets, out-degree, targets)
   extern __shared__ __align__(16) unsigned char smem[];
-  const int cap = a.lds_nodes;
-  double* dH = reinterpret_cast<double*>(smem);
-  float* Fl = reinterpret_cast<float*>(smem + (size_t)cap * 8);
-  int32_t* lptr = reinterpret_cast<int32_t*>(smem + (size_t)cap * 12);
-  int32_t* odeg = reinterpret_cast<int32_t*>(smem + (size_t)cap * 16 + 4);
-  uint32_t* lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4);
   const int p = blockIdx.x;
-  const int lo = a.part_ptr[p], np = a.part_ptr[p + 1] - lo;
-  const int lbase = a.loc_ptr[lo];
-  const int nl = a.loc_ptr[lo + np] - lbase;
-  const bool lidx_in_lds = nl + 2 <= a.lds_edges;
-  // the LDS copy keeps the parity of lbase so that it moves whole 32-bit words
-  const uint16_t* lidx = lidx_in_lds ? reinterpret_cast<const uint16_t*>(lidx_words) + (lbase & 1)
-                                     : a.loc_idx + lbase;
+  const PartView v = part_view(a, smem, p);
 
-  // ---- 1. load the partition (several loads in flight per thread)
-  {
-    constexpr int U = 4;
-    for (int i0 = tid; i0 < np; i0 += U * BLOCK) {
-      float f[U];
-      int32_t lp[U], c0[U], c1[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        if (i < np) {
-          f[u] = a.F[lo + i];
-          lp[u] = a.loc_ptr[lo + i];
-          c0[u] = a.col_ptr[lo + i];
-          c1[u] = a.col_ptr[lo + i + 1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        if (i < np) {
-          Fl[i] = f[u];
-          dH[i] = 0.0;
-          lptr[i] = lp[u] - lbase;
-          odeg[i] = c1[u] - c0[u];
-        }
-      }
-    }
-  }
-  if (tid == 0) lptr[np] = nl;
-  if (lidx_in_lds) {
-    constexpr int U = 8;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.loc_idx) + (lbase >> 1);
-    const int words = ((lbase & 1) + nl + 1) >> 1;
-    for (int w0 = tid; w0 < words; w0 += U * BLOCK) {
-      uint32_t v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (w0 + u * BLOCK < words) v[u] = src[w0 + u * BLOCK];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (w0 + u * BLOCK < words) lidx_words[w0 + u * BLOCK] = v[u];
-    }
-  }
-  __syncthreads();
-
-  // ---- 2. outside fluid
-  for (int h = a.part_heavy[p] + tid; h < a.part_heavy[p + 1]; h += BLOCK) {
-    Fl[a.heavy_rows[h] - lo] += (float)a.heavy_in[h];  // summed by k_part_heavy just before
-    a.heavy_in[h] = 0.0;
-  }
-  {
-    const int e0 = a.ext_ptr[p], e1 = a.ext_ptr[p + 1];
-    int e = e0 + tid;
-    for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {  // four gathers in flight
-      const int32_t s0 = a.ext_src[e], s1 = a.ext_src[e + BLOCK], s2 = a.ext_src[e + 2 * BLOCK],
-                    s3 = a.ext_src[e + 3 * BLOCK];
-      const uint16_t r0 = a.ext_row[e], r1 = a.ext_row[e + BLOCK], r2 = a.ext_row[e + 2 * BLOCK],
-                     r3 = a.ext_row[e + 3 * BLOCK];
-      const float v0 = S_in[s0], v1 = S_in[s1], v2 = S_in[s2], v3 = S_in[s3];
-      if (v0 != 0.f) atomicAdd(&Fl[r0], v0);
-      if (v1 != 0.f) atomicAdd(&Fl[r1], v1);
-      if (v2 != 0.f) atomicAdd(&Fl[r2], v2);
-      if (v3 != 0.f) atomicAdd(&Fl[r3], v3);
-    }
-    for (; e < e1; e += BLOCK) {
-      const float v = S_in[a.ext_src[e]];
-      if (v != 0.f) atomicAdd(&Fl[a.ext_row[e]], v);
-    }
-  }
-  __syncthreads();
-
-  // ---- 3. local threshold sweeps at one T until none passes (at most m)
-  const float T = (float)a.ctrl->T;
-  const float d = a.d;
+  part_load<BLOCK>(a, v);
+  part_inflow<BLOCK, false>(a, v, p, S_in, 0, 0);
   double edges = 0, diffs = 0;
-  for (int s = 0; s < a.m; ++s) {
-    int passed = 0;
-    for (int base = wave * 64; base < np; base += NW * 64) {
-      const int i = base + lane;
-      float sent = 0.f;
-      int ldeg = 0, src0 = 0;
-      float w = 0.f;
-      if (i < np && fabsf(Fl[i]) > T) {
-        sent = atomicExch(&Fl[i], 0.f);
-        dH[i] += (double)sent;
-        src0 = lptr[i];
-        ldeg = lptr[i + 1] - src0;
-        const int od = odeg[i];
-        w = od > 0 ? sent * (d / (float)od) : 0.f;
-        edges += (double)od;
-        diffs += 1.0;
-        passed = 1;
-      }
-      // out-links of the passing nodes laid end to end; each lane takes every
-      // 64th one. The owner of slot e is found by marking each segment's first
-      // slot of the window in LDS and taking a running max across the lanes.
-      // Two windows per step keep two dependency chains in flight.
-      const int incl = wave_incl_scan_dpp(ldeg);
-      const int total = __builtin_amdgcn_readlane(incl, 63);
-      if (total == 0) continue;
-      const int excl = incl - ldeg;
-      s_off[wave][lane] = src0 - excl;
-      s_w[wave][lane] = w;
-      for (int e0 = 0; e0 < total; e0 += 128) {
-        s_mark[wave][0][lane] = 0;
-        s_mark[wave][1][lane] = 0;
-        __builtin_amdgcn_wave_barrier();
-        if (ldeg > 0 && incl > e0 && excl < e0 + 64)
-          s_mark[wave][0][max(excl, e0) - e0] = (uint8_t)(lane + 1);
-        if (ldeg > 0 && incl > e0 + 64 && excl < e0 + 128)
-          s_mark[wave][1][max(excl, e0 + 64) - e0 - 64] = (uint8_t)(lane + 1);
-        __builtin_amdgcn_wave_barrier();
-        const int ownA = wave_incl_max_dpp((int)s_mark[wave][0][lane]) - 1;
-        const int ownB = max(wave_incl_max_dpp((int)s_mark[wave][1][lane]) - 1, 0);
-        const int eA = e0 + lane, eB = e0 + 64 + lane;
-        const int tA = eA < total ? (int)lidx[s_off[wave][ownA] + eA] : -1;
-        const int tB = eB < total ? (int)lidx[s_off[wave][ownB] + eB] : -1;
-        const float wA = s_w[wave][ownA], wB = s_w[wave][ownB];
-        if (tA >= 0) atomicAdd(&Fl[tA], wA);  // ds_add_f32
-        if (tB >= 0) atomicAdd(&Fl[tB], wB);
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    if (!__syncthreads_or(passed)) break;  // barrier + "did any node pass"
-  }
+  part_sweeps<BLOCK>(a, v, (float)a.ctrl->T, edges, diffs);
 
   // ---- 4. write back, publish p_i dH_i, partial sums
   double resid = 0, fmx = 0;
   {
     constexpr int U = 4;
-    for (int i0 = tid; i0 < np; i0 += U * BLOCK) {
+    for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
       double hv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
-        hv[u] = (i < np && dH[i] != 0.0) ? a.H[lo + i] : 0.0;
+        hv[u] = (i < v.np && v.dH[i] != 0.0) ? a.H[v.lo + i] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
-        if (i >= np) continue;
-        const float f = Fl[i];
-        const double dh = dH[i];
-        a.F[lo + i] = f;
+        if (i >= v.np) continue;
+        const float f = v.Fl[i];
+        const double dh = v.dH[i];
+        a.F[v.lo + i] = f;
         float so = 0.f;
         if (dh != 0.0) {
-          a.H[lo + i] = hv[u] + dh;
-          const int od = odeg[i];
+          a.H[v.lo + i] = hv[u] + dh;
+          const int od = v.odeg[i];
           if (od > 0) {
             so = (float)(a.dd * dh / (double)od);
             // in flight to the outside targets of i
-            resid += fabs((double)so) * (double)(od - (lptr[i + 1] - lptr[i]));
+            resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
           }
         }
-        S_out[lo + i] = so;
+        S_out[v.lo + i] = so;
         resid += fabs((double)f);
         fmx = fmax(fmx, fabs((double)f));
       }
@@ -445,30 +526,13 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   }
 
   // ---- 5. per-workgroup sums; the last workgroup finishes the launch
-  resid = wave_sum(resid);
-  fmx = wave_maxd(fmx);
-  edges = wave_sum(edges);
-  diffs = wave_sum(diffs);
-  if (lane == 0) {
-    red[0][wave] = resid;
-    red[1][wave] = fmx;
-    red[2][wave] = edges;
-    red[3][wave] = diffs;
-  }
-  __syncthreads();
+  block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
   if (tid == 0) {
-    double r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-    for (int w = 0; w < NW; ++w) {
-      r0 += red[0][w];
-      r1 = fmax(r1, red[1][w]);
-      r2 += red[2][w];
-      r3 += red[3][w];
-    }
     double* q = a.partials + (size_t)kStride * p;
-    __hip_atomic_store(&q[0], r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&q[1], r1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&q[2], r2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&q[3], r3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q[0], resid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q[1], fmx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q[2], edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q[3], diffs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int t = __hip_atomic_fetch_add(&a.counters[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     s_last = t == a.K - 1;
   }
@@ -482,26 +546,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
     E += __hip_atomic_load(&q[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     P += __hip_atomic_load(&q[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  D = wave_sum(D);
-  E = wave_sum(E);
-  P = wave_sum(P);
-  M = wave_maxd(M);
-  __syncthreads();
-  if (lane == 0) {
-    red[0][wave] = D;
-    red[1][wave] = M;
-    red[2][wave] = E;
-    red[3][wave] = P;
-  }
-  __syncthreads();
+  block_reduce4<BLOCK>(D, M, E, P, red);
   if (tid == 0) {
-    D = 0, M = 0, E = 0, P = 0;
-    for (int w = 0; w < NW; ++w) {
-      D += red[0][w];
-      M = fmax(M, red[1][w]);
-      E += red[2][w];
-      P += red[3][w];
-    }
     Ctrl* ctrl = a.ctrl;
     ctrl->sum_abs = D;
     ctrl->edges += (unsigned long long)E;
@@ -515,6 +561,153 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
       ctrl->T = Tn;
     }
     a.counters[1] = 0;  // finish count of the next launch
+  }
+}
+
+// ---------------------------------------------------- the resident sweep
+// Every value one workgroup of the resident sweep hands to another (published
+// shares, partial sums, heavy-row sums, the votes) is written and read with
+// agent-scope atomics, which bypass the per-XCD L2s, so a grid barrier needs
+// no cache maintenance: each thread waits until its own stores are
+// acknowledged, and thread 0 meets the others on two agent-scope words.
+__device__ __forceinline__ void wait_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // s_waitcnt vmcnt(0)
+}
+
+// Grid barrier of a cooperative launch (every workgroup resident): arrival
+// counter bar[0], generation bar[1]. Workgroups pass the barriers in the same
+// order and count them in `gen`. A wait longer than spin_limit polls sets
+// ctrl->err = 2 and returns false; the caller then leaves the kernel, so every
+// wave exits even if some workgroup never arrives.
+__device__ bool grid_sync(int* bar, int K, int& gen, int spin_limit, int* err, int* s_ok) {
+  wait_stores();
+  __syncthreads();
+  const int target = gen + 1;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const int t = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == K - 1) {
+      __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wait_stores();  // the reset lands before the release of the waiters
+      __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > spin_limit) {
+          ok = 0;
+          __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  gen = target;
+  return *s_ok != 0;
+}
+
+// The partitioned sweep with every partition resident for a whole stage: the
+// partition is loaded into LDS once and stays there across threshold levels.
+// One level: outside inflow, up to m local sweeps at T, H += dH and the shares
+// p_i dH_i published; grid barrier; every workgroup reduces the same
+// per-workgroup sums in the same order, so all take the same stop decision and
+// the same next T (T / alpha). The shares alternate between two buffers, so
+// one barrier per level suffices. F goes back to memory when the stage ends.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_limit) {
+  const int tid = threadIdx.x;
+  constexpr int NW = BLOCK / 64;
+  __shared__ double red[4][NW];
+  __shared__ int s_ok;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int p = blockIdx.x;
+  const PartView v = part_view(a, smem, p);
+  int* bar = a.counters + 2;
+  int* err = &a.ctrl->err;
+  const double target = a.ctrl->target;
+  double T = a.ctrl->T;
+  int gen = 0, parity = 0, done = 0, levels = 0;
+
+  part_load<BLOCK>(a, v);
+  for (; levels < a.max_levels; ++levels) {
+    const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
+    float* S_out = a.S + (size_t)parity * a.n;
+    item_sums<true>(a, S_in, (int64_t)p * NW + (tid >> 6), (int64_t)a.K * NW, a.epoch0 + levels);
+    if (!part_inflow<BLOCK, true>(a, v, p, S_in, a.epoch0 + levels, spin_limit)) return;
+    double edges = 0, diffs = 0;
+    part_sweeps<BLOCK>(a, v, (float)T, edges, diffs);
+
+    // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
+    double resid = 0, fmx = 0;
+    for (int i = tid; i < v.np; i += BLOCK) {
+      const float f = v.Fl[i];
+      const double dh = v.dH[i];
+      float so = 0.f;
+      if (dh != 0.0) {
+        a.H[v.lo + i] += dh;
+        v.dH[i] = 0.0;
+        const int od = v.odeg[i];
+        if (od > 0) {
+          so = (float)(a.dd * dh / (double)od);
+          resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
+        }
+      }
+      st_agent(&S_out[v.lo + i], so);
+      resid += fabs((double)f);
+      fmx = fmax(fmx, fabs((double)f));
+    }
+    // per-workgroup sums and the abort vote go to the slots of this level's
+    // parity: a workgroup can reach the next level's publish while another
+    // still reads this level's slots, never the one after
+    double* part = a.partials + (size_t)parity * a.K * kStride;
+    block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
+    if (tid == 0) {
+      double* q = part + (size_t)kStride * p;
+      st_agent(&q[0], resid);
+      st_agent(&q[1], fmx);
+      st_agent(&q[2], edges);
+      st_agent(&q[3], diffs);
+      if (p == 0) st_agent(&bar[2 + parity], ld_system(a.abort_flag) != 0 ? 1 : 0);
+    }
+    if (!grid_sync(bar, a.K, gen, spin_limit, err, &s_ok)) return;
+
+    // the same global sums in every workgroup
+    double D = 0, M = 0, E = 0, P = 0;
+    for (int k = tid; k < a.K; k += BLOCK) {
+      const double* q = part + (size_t)kStride * k;
+      D += ld_agent(&q[0]);
+      M = fmax(M, ld_agent(&q[1]));
+      E += ld_agent(&q[2]);
+      P += ld_agent(&q[3]);
+    }
+    block_reduce4<BLOCK>(D, M, E, P, red);
+    if (p == 0 && tid == 0) {
+      Ctrl* ctrl = a.ctrl;
+      ctrl->sum_abs = D;
+      ctrl->edges += (unsigned long long)E;
+      ctrl->diffusions += (unsigned long long)P;
+      ctrl->sweeps += 1;
+    }
+    if (D <= target) {
+      done = 1;
+      ++levels;
+      break;
+    }
+    if (ld_agent(&bar[2 + parity])) {
+      ++levels;
+      break;
+    }
+    double Tn = T / (double)a.alpha;
+    if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
+    T = Tn;
+    parity ^= 1;
+  }
+  for (int i = tid; i < v.np; i += BLOCK) a.F[v.lo + i] = v.Fl[i];
+  if (p == 0 && tid == 0) {
+    a.ctrl->T = T;
+    a.ctrl->done = done;
   }
 }
 
@@ -543,8 +736,10 @@ void free_part_plan(ditr_graph* g) {
   PartPlan& q = g->pp;
   for (void* p : {(void*)q.pid, (void*)q.loc_ptr, (void*)q.loc_idx, (void*)q.pw, (void*)q.ext_deg,
                   (void*)q.ext_ptr, (void*)q.ext_src, (void*)q.ext_row, (void*)q.heavy_rows,
-                  (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.heavy_edge_row, (void*)q.S,
-                  (void*)q.heavy_in, (void*)q.partials, (void*)q.counters})
+                  (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.item_row, (void*)q.item_beg,
+                  (void*)q.item_end, (void*)q.part_items, (void*)q.item_sum, (void*)q.item_flag,
+                  (void*)q.short_items, (void*)q.long_items,
+                  (void*)q.S, (void*)q.partials, (void*)q.counters, (void*)q.order})
     (void)hipFree(p);
   q = PartPlan();
 }
@@ -629,12 +824,48 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
       ph[k] = (int32_t)r;
     }
   }
-  PP_TRY(hipMalloc((void**)&q.heavy_edge_row, sizeof(int32_t) * std::max(1, nheavy_e)));
-  if (nh > 0)
-    k_heavy_edge_rows<<<std::min(nh, 4096), 256, 0, st>>>(nh, q.heavy_rows, heavy_ptr, q.heavy_edge_row);
-  PP_TRY(hipGetLastError());
+  {
+    // heavy items: the external in-links of each heavy row cut in pieces of
+    // kItem, grouped by partition (heavy rows ascend, partitions are ranges)
+    std::vector<int32_t> hp(n + 1);
+    PP_TRY(hipMemcpyAsync(hp.data(), heavy_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    PP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> irow, ibeg, iend, pit(K + 1);
+    size_t r = 0;
+    for (int k = 0; k < K; ++k) {
+      pit[k] = (int32_t)irow.size();
+      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
+      for (; r < rows.size() && rows[r] < hi; ++r)
+        for (int32_t b = hp[rows[r]]; b < hp[rows[r] + 1]; b += kItem) {
+          irow.push_back((int32_t)(rows[r] - lo));
+          ibeg.push_back(b);
+          iend.push_back(std::min(b + kItem, hp[rows[r] + 1]));
+        }
+    }
+    pit[K] = (int32_t)irow.size();
+    q.n_items = (int32_t)irow.size();
+    std::vector<int32_t> sh, lg;
+    for (int32_t k = 0; k < q.n_items; ++k) (iend[k] - ibeg[k] <= 64 ? sh : lg).push_back(k);
+    q.n_short = (int32_t)sh.size();
+    q.n_long = (int32_t)lg.size();
+    auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
+      HIP_TRY(hipMalloc((void**)dst, sizeof(int32_t) * std::max<size_t>(1, v.size())));
+      if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
+      return DITR_OK;
+    };
+    int urc = up(&q.item_row, irow);
+    if (!urc) urc = up(&q.item_beg, ibeg);
+    if (!urc) urc = up(&q.item_end, iend);
+    if (!urc) urc = up(&q.part_items, pit);
+    if (!urc) urc = up(&q.short_items, sh);
+    if (!urc) urc = up(&q.long_items, lg);
+    if (urc) { cleanup(); return urc; }
+    PP_TRY(hipMalloc((void**)&q.item_sum, sizeof(double) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMalloc((void**)&q.item_flag, sizeof(int) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMemset(q.item_sum, 0, sizeof(double) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMemset(q.item_flag, 0, sizeof(int) * std::max<size_t>(1, irow.size())));
+  }
   q.n_heavy = nh;
-  q.n_chunks = (int32_t)(((int64_t)nheavy_e + kHeavyChunk - 1) / kHeavyChunk);
   PP_TRY(hipMalloc((void**)&q.part_heavy, sizeof(int32_t) * (K + 1)));
   PP_TRY(hipMemcpy(q.part_heavy, ph.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice));
   PP_TRY(hipMalloc((void**)&q.pw, sizeof(float) * n));
@@ -642,10 +873,9 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   k_weights<<<gb, 256, 0, st>>>(n, g->col_ptr, q.loc_ptr, (float)g->d, q.pw, q.ext_deg);
   PP_TRY(hipGetLastError());
   PP_TRY(hipMalloc((void**)&q.S, sizeof(float) * 2 * n));
-  PP_TRY(hipMalloc((void**)&q.heavy_in, sizeof(double) * std::max(1, nh)));
-  PP_TRY(hipMalloc((void**)&q.counters, sizeof(int) * 2));
-  PP_TRY(hipMemset(q.counters, 0, sizeof(int) * 2));
-  PP_TRY(hipMalloc((void**)&q.partials, sizeof(double) * kStride * K));
+  PP_TRY(hipMalloc((void**)&q.counters, sizeof(int) * kCounters));
+  PP_TRY(hipMemset(q.counters, 0, sizeof(int) * kCounters));
+  PP_TRY(hipMalloc((void**)&q.partials, sizeof(double) * kStride * 2 * K));
   {
     std::vector<int32_t> lp(K + 1);
     int32_t* d_lp = nullptr;
@@ -659,6 +889,27 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     int32_t mx = 0;
     for (int k = 0; k < K; ++k) mx = std::max(mx, lp[k + 1] - lp[k]);
     q.max_local_edges = mx;
+  }
+  {
+    // visiting order of each partition's nodes: falling local out-degree
+    // (stable counting sort), so that the 64 lanes of a wave push lists of
+    // about the same length
+    std::vector<int32_t> lp(n + 1);
+    PP_TRY(hipMemcpyAsync(lp.data(), q.loc_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    PP_TRY(hipStreamSynchronize(st));
+    std::vector<uint16_t> ord(n);
+    std::vector<int32_t> cnt;
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
+      int32_t dmax = 0;
+      for (int64_t i = lo; i < hi; ++i) dmax = std::max(dmax, lp[i + 1] - lp[i]);
+      cnt.assign((size_t)dmax + 2, 0);
+      for (int64_t i = lo; i < hi; ++i) ++cnt[dmax - (lp[i + 1] - lp[i]) + 1];
+      for (int32_t b = 1; b <= dmax + 1; ++b) cnt[b] += cnt[b - 1];
+      for (int64_t i = lo; i < hi; ++i) ord[lo + cnt[dmax - (lp[i + 1] - lp[i])]++] = (uint16_t)(i - lo);
+    }
+    PP_TRY(hipMalloc((void**)&q.order, sizeof(uint16_t) * std::max<int64_t>(1, n)));
+    PP_TRY(hipMemcpy(q.order, ord.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
   }
   q.n_local = nloc;
   q.n_ext = nlight;
@@ -675,43 +926,46 @@ __global__ void k_zero_i32p(int* p, int n) {
 
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g) {
   const PartPlan& q = g->pp;
-  k_zero_i32p<<<1, 64, 0, c->stream>>>(q.counters, 2);
+  k_zero_i32p<<<1, 64, 0, c->stream>>>(q.counters, kCounters);
   k_zero_f32p<<<std::min<int64_t>(4096, (2 * g->n + 255) / 256), 256, 0, c->stream>>>(q.S, 2 * g->n);
-  if (q.n_heavy > 0)
-    k_zero_f64p<<<std::min(1024, (q.n_heavy + 255) / 256), 256, 0, c->stream>>>(
-        q.heavy_in, (int64_t)q.n_heavy);
   HIP_TRY(hipGetLastError());
   return DITR_OK;
 }
 
-// LDS of a partition workgroup: 20 bytes per node (+4) and 2 bytes per local
+// LDS of a partition workgroup: 22 bytes per node (+8) and 2 bytes per local
 // target slot (two spare slots let the targets move as aligned 32-bit words)
 size_t part_lds_bytes(int nodes, int local_edges) {
-  return (size_t)nodes * 20 + 4 + (size_t)local_edges * 2 + 16;
+  return (size_t)nodes * 20 + 4 + (((size_t)nodes * 2 + 3) & ~(size_t)3) + (size_t)local_edges * 2 + 16;
 }
 
+// dynamic LDS both partition kernels may take (the larger static part counts)
 int part_configure(ditr_ctx* c) {
-  hipFuncAttributes attr;
-  if (hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&k_part_sweep<kPB>)) != hipSuccess) {
+  hipFuncAttributes as, ar;
+  if (hipFuncGetAttributes(&as, reinterpret_cast<const void*>(&k_part_sweep<kPB>)) != hipSuccess ||
+      hipFuncGetAttributes(&ar, reinterpret_cast<const void*>(&k_part_resident<kPB>)) != hipSuccess) {
     (void)hipGetLastError();
     return set_error(DITR_EHIP, "hipFuncGetAttributes failed");
   }
+  const size_t stat = std::max(as.sharedSizeBytes, ar.sharedSizeBytes);
   for (size_t total : {c->lds_per_cu, c->lds_per_block}) {
-    if (total <= attr.sharedSizeBytes + 64) continue;
-    const size_t dyn = total - attr.sharedSizeBytes;
+    if (total <= stat + 64) continue;
+    const size_t dyn = total - stat;
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_sweep<kPB>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_resident<kPB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess) {
       c->part_lds_dyn = dyn;
       return DITR_OK;
     }
     (void)hipGetLastError();
   }
-  c->part_lds_dyn = c->lds_per_block > attr.sharedSizeBytes ? c->lds_per_block - attr.sharedSizeBytes : 0;
+  c->part_lds_dyn = c->lds_per_block > stat ? c->lds_per_block - stat : 0;
   return DITR_OK;
 }
 
-int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                       int nlaunch, hipEvent_t* ev) {
+namespace {
+int part_args(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m, PartArgs* out,
+              size_t* lds) {
   const PartPlan& q = g->pp;
   PartArgs a;
   a.n = g->n;
@@ -721,26 +975,35 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   a.col_ptr = g->col_ptr;
   a.loc_ptr = q.loc_ptr;
   a.loc_idx = q.loc_idx;
+  a.order = q.order;
   a.pw = q.pw;
   a.ext_deg = q.ext_deg;
   a.ext_ptr = q.ext_ptr;
   a.ext_src = q.ext_src;
   a.ext_row = q.ext_row;
-  a.heavy_rows = q.heavy_rows;
-  a.part_heavy = q.part_heavy;
   a.heavy_src = q.heavy_src;
-  a.heavy_edge_row = q.heavy_edge_row;
-  a.n_heavy_edges = q.n_heavy_edges;
+  a.part_items = q.part_items;
+  a.item_row = q.item_row;
+  a.item_beg = q.item_beg;
+  a.item_end = q.item_end;
+  a.item_sum = q.item_sum;
+  a.item_flag = q.item_flag;
+  a.short_items = q.short_items;
+  a.long_items = q.long_items;
+  a.n_items = q.n_items;
+  a.n_short = q.n_short;
+  a.n_long = q.n_long;
+  a.epoch0 = 0;
   a.F = f;
   a.H = h;
   a.S = q.S;
-  a.heavy_in = q.heavy_in;
   a.partials = q.partials;
   a.counters = q.counters;
-  a.n_chunks = q.n_chunks;
   a.ctrl = c->ctrl;
+  a.abort_flag = c->abort_dev;
   a.n_heavy = q.n_heavy;
   a.lds_nodes = std::max(1, g->max_part);
+  a.max_levels = 0;
   a.alpha = (float)alpha;
   a.d = (float)g->d;
   a.dd = g->d;
@@ -750,13 +1013,66 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   // local targets go to LDS when the largest partition's fit beside its nodes
   const int64_t room = ((int64_t)c->part_lds_dyn - (int64_t)part_lds_bytes(a.lds_nodes, 0)) / 2;
   a.lds_edges = (int)std::max<int64_t>(0, std::min<int64_t>(room, (int64_t)q.max_local_edges + 2));
-  const size_t lds = part_lds_bytes(a.lds_nodes, a.lds_edges);
+  *lds = part_lds_bytes(a.lds_nodes, a.lds_edges);
+  *out = a;
+  return DITR_OK;
+}
+}  // namespace
+
+int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
+                       int nlaunch, hipEvent_t* ev) {
+  PartArgs a;
+  size_t lds = 0;
+  int rc = part_args(c, g, f, h, alpha, m, &a, &lds);
+  if (rc) return rc;
+  const PartPlan& q = g->pp;
   for (int s = 0; s < nlaunch; ++s) {
-    if (q.n_chunks > 0) k_part_heavy<<<q.n_chunks, 256, 0, c->stream>>>(a, s & 1);
+    const int64_t units = (q.n_short + 7) / 8 + q.n_long;
+    if (units > 0)
+      k_part_items<<<(unsigned)std::min<int64_t>((units + 3) / 4, 16384), 256, 0, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s], c->stream));
     k_part_sweep<kPB><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s + 1], c->stream));
   }
   HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+// Whether every partition workgroup of g can be resident at once (one
+// cooperative launch of K workgroups).
+int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits) {
+  *fits = false;
+  PartArgs a;
+  size_t lds = 0;
+  int rc = part_args(c, g, nullptr, nullptr, 1.5, 1, &a, &lds);
+  if (rc) return rc;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB>, kPB, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return DITR_OK;
+  }
+  *fits = (int64_t)per_cu * c->num_cus >= g->K;
+  return DITR_OK;
+}
+
+int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
+                         int max_levels) {
+  PartArgs a;
+  size_t lds = 0;
+  int rc = part_args(c, g, f, h, alpha, m, &a, &lds);
+  if (rc) return rc;
+  a.max_levels = max_levels;
+  // epochs of this launch's levels: above every flag an earlier launch stored
+  const PartPlan& q = g->pp;
+  if ((int64_t)q.epoch + max_levels + 1 >= (int64_t)1 << 30) {  // restart the epochs
+    HIP_TRY(hipMemsetAsync(q.item_flag, 0, sizeof(int) * std::max(1, q.n_items), c->stream));
+    const_cast<PartPlan&>(q).epoch = 0;
+  }
+  a.epoch0 = q.epoch + 1;
+  const_cast<PartPlan&>(q).epoch += max_levels + 1;
+  int spin_limit = 1 << 24;  // polls of about a microsecond: a stuck wait ends within seconds
+  void* args[] = {&a, &spin_limit};
+  HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_part_resident<kPB>), dim3(a.K),
+                                     dim3(kPB), args, (unsigned)lds, c->stream));
   return DITR_OK;
 }

@@ -21,6 +21,7 @@ EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
 PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
+FLAG_NO_RESIDENT = 2
 GNN_PARAMS = 9409
 GNN_ACT_X, GNN_ACT_PX, GNN_ACT_H1, GNN_ACT_PH1, GNN_ACT_H2 = 0, 1, 2, 3, 4
 
