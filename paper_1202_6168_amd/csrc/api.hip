@@ -274,9 +274,9 @@ int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
     return rc;
   }
   // a partition's nodes must fit the LDS of both partitioned kernels
-  // (12 bytes per node for the asynchronous one, 22 for the partitioned sweep)
+  // (12 bytes per node for the asynchronous one, 20 for the partitioned sweep)
   const int64_t cap_nodes = std::min<int64_t>(
-      65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 22)));
+      65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 20)));
   int64_t K;
   if (o.part_nodes > 0) {
     K = (n + o.part_nodes - 1) / o.part_nodes;
@@ -474,7 +474,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     const double stage = (!refreshed && r > o.refresh_at * b1) ? std::max(target, o.refresh_at * b1)
                                                                : 0.5 * target;
     // the threshold continues from the previous round (never above max|F| / alpha)
-    const double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha) : fmax / o.alpha;
+    double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha) : fmax / o.alpha;
+    if (mode == DITR_MODE_PARTITION) T0 = std::max(T0, r * kPartTFloor);
     rc = launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
     if (mode == DITR_MODE_PARTITION) {

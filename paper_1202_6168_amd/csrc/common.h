@@ -108,6 +108,9 @@ struct ditr_graph {
 constexpr int kHeavyRow = 64;     // in-degree above which a row's in-links are split in chunks
 constexpr int kHeavyChunk = 2048; // in-links per chunk workgroup
 constexpr int kPartHeavy = 8;     // external in-links above which a row's inflow is summed in items
+// lowest threshold of the partitioned sweep relative to the total fluid (its
+// LDS fluid is fixed point in units of T 2^-32)
+constexpr double kPartTFloor = 1.0 / 268435456.0;  // 2^-28
 
 // ---- error reporting (api.hip) ------------------------------------------
 int set_error(int code, const char* fmt, ...);

@@ -191,15 +191,40 @@ struct PartArgs {
   double dd;  // damping in FP64 for the published shares
 };
 
-// A partition's view of the dynamic LDS: history increment (FP64), fluid
-// (FP32), local CSC offsets, out-degrees, visiting order and, when they fit,
+// Fluid in LDS is fixed point: F = Fq q with q = T 2^-32 for the threshold T
+// of the level, so the test |F| > T is |Fq| > 2^32, a push is an integer LDS
+// atomic (ds_add_u64, several times the rate of the FP32 one on this chip) and
+// the resolution is 2^-32 T (FP32 gives 2^-24 of the value). Signed fluid adds
+// in two's complement; conversions saturate at 2^62 q (T never falls 2^30
+// below the fluid it tests).
+constexpr double kFix = 4294967296.0;  // 2^32
+__device__ __forceinline__ long long to_fixed(double x) {
+  const double lim = 4611686018427387904.0;  // 2^62
+  return __double2ll_rn(fmin(fmax(x, -lim), lim));
+}
+__device__ __forceinline__ void add_fixed(long long* p, long long v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);  // ds_add_u64
+}
+// No node holds more than the total absolute fluid D (fluid in flight
+// included): diffusion only splits and damps it. T therefore never drops below
+// D 2^-28 (kPartTFloor), so no fixed-point value exceeds 2^60. A lower T would
+// not diffuse more on graphs below 2^28 nodes, where some node holds at least
+// D / n of the fluid; without the floor, fluid that only crosses partitions
+// (M = 0 at every level) would let T fall by alpha per level while the fluid
+// falls by d.
+// quantum of the threshold T (a positive floor keeps 1/q finite when T = 0)
+__device__ __forceinline__ double fixed_quantum(double T) { return fmax(T, 1e-280) / kFix; }
+
+// A partition's view of the dynamic LDS, indexed by local id (the partition's
+// nodes renumbered in visiting order: local id r is node lo + order[lo + r]):
+// fluid (fixed point), history increment of the level (FP32, added to the
+// FP64 H when published), local CSC offsets, out-degrees and, when they fit,
 // the local targets.
 struct PartView {
-  double* dH;
-  float* Fl;
+  long long* Fq;
+  float* dH;
   int32_t* lptr;
   int32_t* odeg;
-  uint16_t* ord;
   uint32_t* lidx_words;
   const uint16_t* lidx;
   int lo, np, lbase, nl;
@@ -209,12 +234,11 @@ struct PartView {
 __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* smem, int p) {
   PartView v;
   const int cap = a.lds_nodes;
-  v.dH = reinterpret_cast<double*>(smem);
-  v.Fl = reinterpret_cast<float*>(smem + (size_t)cap * 8);
+  v.Fq = reinterpret_cast<long long*>(smem);
+  v.dH = reinterpret_cast<float*>(smem + (size_t)cap * 8);
   v.lptr = reinterpret_cast<int32_t*>(smem + (size_t)cap * 12);
   v.odeg = reinterpret_cast<int32_t*>(smem + (size_t)cap * 16 + 4);
-  v.ord = reinterpret_cast<uint16_t*>(smem + (size_t)cap * 20 + 4);
-  v.lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4 + (((size_t)cap * 2 + 3) & ~(size_t)3));
+  v.lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4);
   v.lo = a.part_ptr[p];
   v.np = a.part_ptr[p + 1] - v.lo;
   v.lbase = a.loc_ptr[v.lo];
@@ -228,29 +252,35 @@ __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* 
 
 // 1. load the partition into LDS (several loads in flight per thread)
 template <int BLOCK>
-__device__ void part_load(const PartArgs& a, const PartView& v) {
+__device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
   const int tid = threadIdx.x;
   {
     constexpr int U = 4;
     for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
+      int32_t gi[U], lp[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * BLOCK;
+        gi[u] = i < v.np ? v.lo + a.order[v.lo + i] : 0;
+        lp[u] = i < v.np ? a.loc_ptr[v.lo + i] : 0;
+      }
       float f[U];
-      int32_t lp[U], c0[U], c1[U];
+      int32_t c0[U], c1[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
         if (i < v.np) {
-          f[u] = a.F[v.lo + i];
-          lp[u] = a.loc_ptr[v.lo + i];
-          c0[u] = a.col_ptr[v.lo + i];
-          c1[u] = a.col_ptr[v.lo + i + 1];
+          f[u] = a.F[gi[u]];
+          c0[u] = a.col_ptr[gi[u]];
+          c1[u] = a.col_ptr[gi[u] + 1];
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
         if (i < v.np) {
-          v.Fl[i] = f[u];
-          v.dH[i] = 0.0;
+          v.Fq[i] = to_fixed((double)f[u] * inv_q);
+          v.dH[i] = 0.f;
           v.lptr[i] = lp[u] - v.lbase;
           v.odeg[i] = c1[u] - c0[u];
         }
@@ -258,7 +288,6 @@ __device__ void part_load(const PartArgs& a, const PartView& v) {
     }
   }
   if (tid == 0) v.lptr[v.np] = v.nl;
-  for (int i = tid; i < v.np; i += BLOCK) v.ord[i] = a.order[v.lo + i];
   if (v.lidx_in_lds) {
     constexpr int U = 8;
     const uint32_t* src = reinterpret_cast<const uint32_t*>(a.loc_idx) + (v.lbase >> 1);
@@ -341,8 +370,8 @@ __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first_wa
 // were published inside the same kernel, so they are read at agent scope.
 // Returns false on a timed-out wait.
 template <int BLOCK, bool RESIDENT>
-__device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const float* S_in, int epoch,
-                            int spin_limit) {
+__device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const float* S_in, double inv_q,
+                            int epoch, int spin_limit) {
   const int tid = threadIdx.x;
   auto ld = [&](int32_t s) { return RESIDENT ? ld_agent(&S_in[s]) : S_in[s]; };
   const int e0 = a.ext_ptr[p], e1 = a.ext_ptr[p + 1];
@@ -353,14 +382,14 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
     const uint16_t r0 = a.ext_row[e], r1 = a.ext_row[e + BLOCK], r2 = a.ext_row[e + 2 * BLOCK],
                    r3 = a.ext_row[e + 3 * BLOCK];
     const float v0 = ld(s0), v1 = ld(s1), v2 = ld(s2), v3 = ld(s3);
-    if (v0 != 0.f) atomicAdd(&v.Fl[r0], v0);
-    if (v1 != 0.f) atomicAdd(&v.Fl[r1], v1);
-    if (v2 != 0.f) atomicAdd(&v.Fl[r2], v2);
-    if (v3 != 0.f) atomicAdd(&v.Fl[r3], v3);
+    if (v0 != 0.f) add_fixed(&v.Fq[r0], to_fixed((double)v0 * inv_q));
+    if (v1 != 0.f) add_fixed(&v.Fq[r1], to_fixed((double)v1 * inv_q));
+    if (v2 != 0.f) add_fixed(&v.Fq[r2], to_fixed((double)v2 * inv_q));
+    if (v3 != 0.f) add_fixed(&v.Fq[r3], to_fixed((double)v3 * inv_q));
   }
   for (; e < e1; e += BLOCK) {
     const float x = ld(a.ext_src[e]);
-    if (x != 0.f) atomicAdd(&v.Fl[a.ext_row[e]], x);
+    if (x != 0.f) add_fixed(&v.Fq[a.ext_row[e]], to_fixed((double)x * inv_q));
   }
   bool ok = true;
   for (int k = a.part_items[p] + tid; k < a.part_items[p + 1]; k += BLOCK) {
@@ -377,35 +406,32 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
       if (!ok) break;
     }
     const double x = RESIDENT ? ld_agent(&a.item_sum[k]) : a.item_sum[k];
-    if (x != 0.0) atomicAdd(&v.Fl[a.item_row[k]], (float)x);
+    if (x != 0.0) add_fixed(&v.Fq[a.item_row[k]], to_fixed(x * inv_q));
   }
   return __syncthreads_and(ok) != 0;
 }
 
 // 3. local threshold sweeps at one T until none passes (at most m). Each
-// thread takes one node of the visiting order at a time (consecutive slots
-// hold nodes of about the same local out-degree, so a wave's lanes finish
-// their lists together) and pushes its share to every local target with LDS
-// atomics, eight targets per step: their loads are issued together, then the
-// adds. TARGETS_LDS: the local targets were copied to LDS (the pointer then has
+// thread takes one node at a time in local-id order (consecutive ids have about
+// the same local out-degree, so a wave's lanes finish their lists together)
+// and pushes its share to every local target with LDS atomics, eight targets
+// per step: their loads are issued together, then the adds. TARGETS_LDS: the local targets were copied to LDS (the pointer then has
 // a known address space and the loop waits on LDS traffic only).
 template <int BLOCK, bool TARGETS_LDS>
-__device__ void part_sweeps_t(const PartArgs& a, const PartView& v, float T, double& edges,
+__device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quantum, double& edges,
                               double& diffs) {
   const uint16_t* __restrict__ lidx =
       TARGETS_LDS ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1) : a.loc_idx + v.lbase;
-  const float d = a.d;
+  const long long Tq = 1LL << 32;  // T in fixed point
   for (int s = 0; s < a.m; ++s) {
     int passed = 0;
-    for (int k = threadIdx.x; k < v.np; k += BLOCK) {
-      const int i = v.ord[k];
-      if (!(fabsf(v.Fl[i]) > T)) continue;
-      const float sent = atomicExch(&v.Fl[i], 0.f);
-      v.dH[i] += (double)sent;
+    for (int i = threadIdx.x; i < v.np; i += BLOCK) {
+      const long long f = v.Fq[i];
+      if (!(f > Tq || f < -Tq)) continue;
+      const long long sq = (long long)atomicExch(reinterpret_cast<unsigned long long*>(&v.Fq[i]), 0ull);
+      v.dH[i] += (float)((double)sq * quantum);
       const int od = v.odeg[i];
-      // FP32 share of the in-LDS fluid; the published shares and the exact
-      // residual use d / #out_i in FP64
-      const float w = od > 0 ? sent * d * __builtin_amdgcn_rcpf((float)od) : 0.f;
+      const long long w = od > 0 ? to_fixed((double)sq * (a.dd / (double)od)) : 0;
       edges += (double)od;
       diffs += 1.0;
       passed = 1;
@@ -416,7 +442,7 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, float T, dou
         for (int q = 0; q < 8; ++q) t[q] = e + q < e1 ? (int)lidx[e + q] : -1;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (t[q] >= 0) atomicAdd(&v.Fl[t[q]], w);  // ds_add_f32
+          if (t[q] >= 0) add_fixed(&v.Fq[t[q]], w);  // ds_add_u64
       }
     }
     if (!__syncthreads_or(passed)) break;  // barrier + "did any node pass"
@@ -424,10 +450,10 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, float T, dou
 }
 
 template <int BLOCK>
-__device__ void part_sweeps(const PartArgs& a, const PartView& v, float T, double& edges,
+__device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum, double& edges,
                             double& diffs) {
-  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, T, edges, diffs);
-  else part_sweeps_t<BLOCK, false>(a, v, T, edges, diffs);
+  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, quantum, edges, diffs);
+  else part_sweeps_t<BLOCK, false>(a, v, quantum, edges, diffs);
 }
 
 // block-wide sums of (resid, edges, diffs) and max of fmx, in a fixed order;
@@ -485,32 +511,39 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   const int p = blockIdx.x;
   const PartView v = part_view(a, smem, p);
 
-  part_load<BLOCK>(a, v);
-  part_inflow<BLOCK, false>(a, v, p, S_in, 0, 0);
+  const double quantum = fixed_quantum(a.ctrl->T);
+  part_load<BLOCK>(a, v, 1.0 / quantum);
+  part_inflow<BLOCK, false>(a, v, p, S_in, 1.0 / quantum, 0, 0);
   double edges = 0, diffs = 0;
-  part_sweeps<BLOCK>(a, v, (float)a.ctrl->T, edges, diffs);
+  part_sweeps<BLOCK>(a, v, quantum, edges, diffs);
 
   // ---- 4. write back, publish p_i dH_i, partial sums
   double resid = 0, fmx = 0;
   {
     constexpr int U = 4;
     for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
+      int32_t gi[U];
       double hv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
-        hv[u] = (i < v.np && v.dH[i] != 0.0) ? a.H[v.lo + i] : 0.0;
+        gi[u] = i < v.np ? v.lo + a.order[v.lo + i] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * BLOCK;
+        hv[u] = (i < v.np && v.dH[i] != 0.f) ? a.H[gi[u]] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int i = i0 + u * BLOCK;
         if (i >= v.np) continue;
-        const float f = v.Fl[i];
-        const double dh = v.dH[i];
-        a.F[v.lo + i] = f;
+        const double f = (double)v.Fq[i] * quantum;
+        const double dh = (double)v.dH[i];
+        a.F[gi[u]] = (float)f;
         float so = 0.f;
         if (dh != 0.0) {
-          a.H[v.lo + i] = hv[u] + dh;
+          a.H[gi[u]] = hv[u] + dh;
           const int od = v.odeg[i];
           if (od > 0) {
             so = (float)(a.dd * dh / (double)od);
@@ -518,9 +551,9 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
             resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
           }
         }
-        S_out[v.lo + i] = so;
-        resid += fabs((double)f);
-        fmx = fmax(fmx, fabs((double)f));
+        S_out[gi[u]] = so;
+        resid += fabs(f);
+        fmx = fmax(fmx, fabs(f));
       }
     }
   }
@@ -558,7 +591,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
     } else {
       double Tn = ctrl->T / (double)a.alpha;  // one threshold level per launch
       if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
-      ctrl->T = Tn;
+      ctrl->T = fmax(Tn, D * kPartTFloor);
     }
     a.counters[1] = 0;  // finish count of the next launch
   }
@@ -630,33 +663,35 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   double T = a.ctrl->T;
   int gen = 0, parity = 0, done = 0, levels = 0;
 
-  part_load<BLOCK>(a, v);
+  double quantum = fixed_quantum(T);
+  part_load<BLOCK>(a, v, 1.0 / quantum);
   for (; levels < a.max_levels; ++levels) {
     const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
     float* S_out = a.S + (size_t)parity * a.n;
     item_sums<true>(a, S_in, (int64_t)p * NW + (tid >> 6), (int64_t)a.K * NW, a.epoch0 + levels);
-    if (!part_inflow<BLOCK, true>(a, v, p, S_in, a.epoch0 + levels, spin_limit)) return;
+    if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, a.epoch0 + levels, spin_limit)) return;
     double edges = 0, diffs = 0;
-    part_sweeps<BLOCK>(a, v, (float)T, edges, diffs);
+    part_sweeps<BLOCK>(a, v, quantum, edges, diffs);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
     double resid = 0, fmx = 0;
     for (int i = tid; i < v.np; i += BLOCK) {
-      const float f = v.Fl[i];
-      const double dh = v.dH[i];
+      const int32_t gi = v.lo + a.order[v.lo + i];
+      const double f = (double)v.Fq[i] * quantum;
+      const double dh = (double)v.dH[i];
       float so = 0.f;
       if (dh != 0.0) {
-        a.H[v.lo + i] += dh;
-        v.dH[i] = 0.0;
+        a.H[gi] += dh;
+        v.dH[i] = 0.f;
         const int od = v.odeg[i];
         if (od > 0) {
           so = (float)(a.dd * dh / (double)od);
           resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
         }
       }
-      st_agent(&S_out[v.lo + i], so);
-      resid += fabs((double)f);
-      fmx = fmax(fmx, fabs((double)f));
+      st_agent(&S_out[gi], so);
+      resid += fabs(f);
+      fmx = fmax(fmx, fabs(f));
     }
     // per-workgroup sums and the abort vote go to the slots of this level's
     // parity: a workgroup can reach the next level's publish while another
@@ -701,10 +736,16 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     }
     double Tn = T / (double)a.alpha;
     if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
+    Tn = fmax(Tn, D * kPartTFloor);
+    // the fluid moves to the quantum of the next threshold
+    const double qn = fixed_quantum(Tn), r = quantum / qn;
+    for (int i = tid; i < v.np; i += BLOCK) v.Fq[i] = to_fixed((double)v.Fq[i] * r);
+    __syncthreads();
     T = Tn;
+    quantum = qn;
     parity ^= 1;
   }
-  for (int i = tid; i < v.np; i += BLOCK) a.F[v.lo + i] = v.Fl[i];
+  for (int i = tid; i < v.np; i += BLOCK) a.F[v.lo + a.order[v.lo + i]] = (float)((double)v.Fq[i] * quantum);
   if (p == 0 && tid == 0) {
     a.ctrl->T = T;
     a.ctrl->done = done;
@@ -893,7 +934,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   {
     // visiting order of each partition's nodes: falling local out-degree
     // (stable counting sort), so that the 64 lanes of a wave push lists of
-    // about the same length
+    // about the same length (computed on the CSC in node order)
     std::vector<int32_t> lp(n + 1);
     PP_TRY(hipMemcpyAsync(lp.data(), q.loc_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
     PP_TRY(hipStreamSynchronize(st));
@@ -910,6 +951,48 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     }
     PP_TRY(hipMalloc((void**)&q.order, sizeof(uint16_t) * std::max<int64_t>(1, n)));
     PP_TRY(hipMemcpy(q.order, ord.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
+    // renumber each partition's nodes by that order: local id r is node
+    // lo + order[lo + r]; the local CSC, the rows of the light external links
+    // and the rows of the heavy items take the new ids
+    std::vector<uint16_t> inv(n);
+    for (int64_t k = 0; k < K; ++k) {
+      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
+      for (int64_t r = 0; r < hi - lo; ++r) inv[lo + ord[lo + r]] = (uint16_t)r;
+    }
+    {
+      std::vector<uint16_t> li((size_t)nloc + 4), li2((size_t)nloc + 4, 0);
+      PP_TRY(hipMemcpy(li.data(), q.loc_idx, sizeof(uint16_t) * nloc, hipMemcpyDeviceToHost));
+      std::vector<int32_t> lp2(n + 1);
+      for (int64_t k = 0; k < K; ++k) {
+        const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
+        int32_t pos = lp[lo];
+        for (int64_t r = 0; r < hi - lo; ++r) {
+          const int64_t i = lo + ord[lo + r];
+          lp2[lo + r] = pos;
+          for (int32_t e = lp[i]; e < lp[i + 1]; ++e) li2[pos++] = inv[lo + li[e]];
+        }
+      }
+      lp2[n] = lp[n];
+      PP_TRY(hipMemcpy(q.loc_ptr, lp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+      PP_TRY(hipMemcpy(q.loc_idx, li2.data(), sizeof(uint16_t) * nloc, hipMemcpyHostToDevice));
+    }
+    {
+      std::vector<int32_t> ep(K + 1);
+      std::vector<uint16_t> er(std::max(1, nlight));
+      PP_TRY(hipMemcpy(ep.data(), q.ext_ptr, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost));
+      if (nlight > 0) PP_TRY(hipMemcpy(er.data(), q.ext_row, sizeof(uint16_t) * nlight, hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < K; ++k)
+        for (int32_t e = ep[k]; e < ep[k + 1]; ++e) er[e] = inv[g->part_ptr_host[k] + er[e]];
+      if (nlight > 0) PP_TRY(hipMemcpy(q.ext_row, er.data(), sizeof(uint16_t) * nlight, hipMemcpyHostToDevice));
+    }
+    if (q.n_items > 0) {
+      std::vector<int32_t> pi(K + 1), ir(q.n_items);
+      PP_TRY(hipMemcpy(pi.data(), q.part_items, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost));
+      PP_TRY(hipMemcpy(ir.data(), q.item_row, sizeof(int32_t) * q.n_items, hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < K; ++k)
+        for (int32_t t = pi[k]; t < pi[k + 1]; ++t) ir[t] = inv[g->part_ptr_host[k] + ir[t]];
+      PP_TRY(hipMemcpy(q.item_row, ir.data(), sizeof(int32_t) * q.n_items, hipMemcpyHostToDevice));
+    }
   }
   q.n_local = nloc;
   q.n_ext = nlight;
@@ -932,10 +1015,10 @@ int launch_part_prepare(ditr_ctx* c, const ditr_graph* g) {
   return DITR_OK;
 }
 
-// LDS of a partition workgroup: 22 bytes per node (+8) and 2 bytes per local
+// LDS of a partition workgroup: 20 bytes per node (+4) and 2 bytes per local
 // target slot (two spare slots let the targets move as aligned 32-bit words)
 size_t part_lds_bytes(int nodes, int local_edges) {
-  return (size_t)nodes * 20 + 4 + (((size_t)nodes * 2 + 3) & ~(size_t)3) + (size_t)local_edges * 2 + 16;
+  return (size_t)nodes * 20 + 4 + (size_t)local_edges * 2 + 16;
 }
 
 // dynamic LDS both partition kernels may take (the larger static part counts)
