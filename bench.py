@@ -27,13 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
-PROFILE = os.path.join(ROOT, "profiles", "k_part_sweep_headline_n1e6.json")
+PROFILE = os.path.join(ROOT, "profiles", "k_part_resident_headline_n1e6.json")
 
 
-def profiled_traffic():
-    """HBM bytes per k_part_sweep launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
-    source changed since those counters were taken."""
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary
+    covers another kernel or the kernel source changed since those counters
+    were taken."""
     import hashlib
 
     try:
@@ -42,6 +43,8 @@ def profiled_traffic():
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest() != prof.get("source_sha256"):
+        return None
+    if prof.get("kernel", "").split("<")[0] != kernel:
         return None
     return prof["traffic_bytes_per_launch"]
 
@@ -289,6 +292,10 @@ def main():
     ksec = sum(s.kernel_seconds for s in stats)
     klaunch = sum(s.timed_launches for s in stats)
     ms_step = 1e3 * wall / args.steps
+    # the resident partitioned sweep is one launch per stage (launches ==
+    # rounds); the per-level relaunch path counts every launch
+    resident = all(s.launches == s.rounds for s in stats)
+    kernel = "k_part_resident" if resident else "k_part_sweep"
     # algorithmic bytes of a diffusion (no reuse on chip): per out-link 4 B index
     # + 8 B FP32 read-modify-write of the target's fluid; per diffused node 4 B
     # column pointer + 8 B fluid read and zero + 16 B FP64 history update
@@ -327,12 +334,12 @@ def main():
         "graph_setup_ms": setup_ms,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_part_sweep",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic(),
+            "traffic": profiled_traffic(kernel),
             "alg_bytes_per_launch": bytes_alg / klaunch if klaunch else None,
             "bytes_per_edge": bytes_alg / edges if edges else None,
             "avg_launch_us": 1e6 * ksec / klaunch if klaunch else None,

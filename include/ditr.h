@@ -113,7 +113,8 @@ typedef struct {
   double b_l1;         /* ||B||_1 */
   double seconds;      /* host wall time of the call */
   double kernel_seconds;  /* with DITR_FLAG_TIME_KERNELS: event-timed diffusion launches */
-  int64_t timed_launches; /* launches covered by kernel_seconds */
+  int64_t timed_launches; /* kernel launches covered by kernel_seconds (a resident
+                             partitioned stage is one launch of many levels) */
   int32_t rounds;      /* outer rounds used */
   int32_t status;      /* same as the return value */
 } ditr_stats;

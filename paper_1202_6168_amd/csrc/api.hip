@@ -501,12 +501,11 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
             rc = DITR_OK;
           }
         }
-        if (!rc && resident) rc = t_end(0);
+        if (!rc && resident) rc = t_end(1);
         if (!rc && resident) rc = read_ctrl(c);
         if (rc) return finish(rc);
         if (resident && c->ctrl_host->err == 2)
           return finish(set_error(DITR_EHIP, "a grid barrier of the resident sweep timed out"));
-        if (resident && timed) st.timed_launches += (int64_t)(c->ctrl_host->sweeps - before);
         if (resident) st.launches += 1;
       }
       // otherwise launches of m local sweeps in batches; the stop flag turns the

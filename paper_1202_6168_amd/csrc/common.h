@@ -49,7 +49,8 @@ struct PartPlan {
   int32_t* pid = nullptr;        // [n] partition of each node
   int32_t* loc_ptr = nullptr;    // [n+1] local CSC: out-links that stay in the partition
   uint16_t* loc_idx = nullptr;   //   target - partition start
-  uint16_t* order = nullptr;     // [n] visiting order inside each partition (falling local degree)
+  uint16_t* inv = nullptr;       // [n] local id of each node: its rank in the partition's
+                                 //   visiting order (falling local out-degree)
   float* pw = nullptr;           // [n] d / #out_i (0 for a dangling node)
   int32_t* ext_deg = nullptr;    // [n] out-links leaving the partition
   int32_t* ext_ptr = nullptr;    // [K+1] external in-links of each partition (light rows)
@@ -57,16 +58,15 @@ struct PartPlan {
   uint16_t* ext_row = nullptr;   //   target - partition start
   int32_t* heavy_rows = nullptr; // rows with more than kPartHeavy external in-links, ascending
   int32_t* part_heavy = nullptr; // [K+1] range of heavy_rows inside each partition
-  int32_t* heavy_src = nullptr;  // external in-links of heavy rows (CSR order)
-  int32_t* item_row = nullptr;   // heavy items (kItem links of one heavy row): local row
-  int32_t* item_beg = nullptr;   //   links [item_beg, item_end) of heavy_src
-  int32_t* item_end = nullptr;
+  int32_t* heavy_src = nullptr;  // external in-links of heavy rows (CSR order; plan build only)
+  int32_t* item_row = nullptr;   // heavy items (at most kItem links of one heavy row): local row
   int32_t* part_items = nullptr; // [K+1] items of each partition
-  double* item_sum = nullptr;    // [n_items] item inflow
-  int* item_flag = nullptr;      // [n_items] epoch of the stored sum (resident sweep)
-  int32_t* short_items = nullptr; // items of at most 64 links
-  int32_t* long_items = nullptr;  // longer items
-  int32_t n_items = 0, n_short = 0, n_long = 0;
+  int32_t* unit_src = nullptr;   // [n_units][8][64] work units of the item sums: source of
+                                 //   slot q of a lane (-1: none)
+  int32_t* unit_meta = nullptr;  // [n_units][64] per lane: (item + 1 for the lane that leads
+                                 //   its group, else 0) << 3 | log2(lanes of the group)
+  unsigned long long* item_word = nullptr;  // [n_items] item inflow: FP32 bits | epoch << 32
+  int32_t n_items = 0, n_units = 0;
   int64_t epoch = 0;             // epochs handed out to resident launches so far
   float* S = nullptr;            // [2][n] published p_i dH_i
   int* counters = nullptr;       // [8] finished workgroups at [1], grid barrier at [2..4]
@@ -107,7 +107,7 @@ struct ditr_graph {
 
 constexpr int kHeavyRow = 64;     // in-degree above which a row's in-links are split in chunks
 constexpr int kHeavyChunk = 2048; // in-links per chunk workgroup
-constexpr int kPartHeavy = 8;     // external in-links above which a row's inflow is summed in items
+constexpr int kPartHeavy = 4;     // external in-links above which a row's inflow is summed in items
 // lowest threshold of the partitioned sweep relative to the total fluid (its
 // LDS fluid is fixed point in units of T 2^-32)
 constexpr double kPartTFloor = 1.0 / 268435456.0;  // 2^-28

@@ -158,22 +158,18 @@ struct PartArgs {
   const int32_t* __restrict__ col_ptr;
   const int32_t* __restrict__ loc_ptr;
   const uint16_t* __restrict__ loc_idx;
-  const uint16_t* __restrict__ order;  // [n] visiting order inside each partition (local ids)
+  const uint16_t* __restrict__ inv;    // [n] local id of each node in its partition
   const float* __restrict__ pw;
   const int32_t* __restrict__ ext_deg;
   const int32_t* __restrict__ ext_ptr;   // [K+1] light external in-links of each partition
   const int32_t* __restrict__ ext_src;
   const uint16_t* __restrict__ ext_row;
-  const int32_t* __restrict__ heavy_src;   // external in-links of the heavy rows, row by row
-  const int32_t* __restrict__ part_items;  // [K+1] heavy items of each partition
-  const int32_t* __restrict__ item_row;    // item -> row - partition start
-  const int32_t* __restrict__ item_beg;    // item -> its links [item_beg, item_end) of heavy_src
-  const int32_t* __restrict__ item_end;
-  double* item_sum;  // [n_items] inflow of one item
-  int* item_flag;    // [n_items] epoch of the level whose item_sum is stored (resident)
-  const int32_t* __restrict__ short_items;  // items of at most 64 links (8 lanes each)
-  const int32_t* __restrict__ long_items;   // longer items (a wave each)
-  int n_items, n_short, n_long;
+  const int32_t* __restrict__ part_items;   // [K+1] heavy items of each partition
+  const int32_t* __restrict__ item_row;     // item -> local row
+  const int32_t* __restrict__ unit_src;     // [n_units][8][64] sources of the item work units
+  const int32_t* __restrict__ unit_meta;    // [n_units][64] lane -> item it leads, group size
+  unsigned long long* item_word;            // [n_items] item inflow bits | epoch << 32
+  int n_items, n_units;
   int epoch0;        // resident: epoch of level 0 (grows across launches)
   float* F;
   double* H;
@@ -216,7 +212,7 @@ __device__ __forceinline__ void add_fixed(long long* p, long long v) {
 __device__ __forceinline__ double fixed_quantum(double T) { return fmax(T, 1e-280) / kFix; }
 
 // A partition's view of the dynamic LDS, indexed by local id (the partition's
-// nodes renumbered in visiting order: local id r is node lo + order[lo + r]):
+// nodes renumbered in visiting order: node lo + j has local id inv[lo + j]):
 // fluid (fixed point), history increment of the level (FP32, added to the
 // FP64 H when published), local CSC offsets, out-degrees and, when they fit,
 // the local targets.
@@ -250,39 +246,34 @@ __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* 
   return v;
 }
 
-// 1. load the partition into LDS (several loads in flight per thread)
+// 1. load the partition into LDS: local CSC offsets in local order, fluid and
+// out-degrees in node order through inv (coalesced; eight nodes per thread in
+// flight)
 template <int BLOCK>
 __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
   const int tid = threadIdx.x;
+  for (int i = tid; i < v.np; i += BLOCK) v.lptr[i] = a.loc_ptr[v.lo + i] - v.lbase;
   {
-    constexpr int U = 4;
-    for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
-      int32_t gi[U], lp[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        gi[u] = i < v.np ? v.lo + a.order[v.lo + i] : 0;
-        lp[u] = i < v.np ? a.loc_ptr[v.lo + i] : 0;
-      }
+    constexpr int U = 8;
+    for (int j0 = tid; j0 < v.np; j0 += U * BLOCK) {
+      int r[U], c0[U], c1[U];
       float f[U];
-      int32_t c0[U], c1[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        if (i < v.np) {
-          f[u] = a.F[gi[u]];
-          c0[u] = a.col_ptr[gi[u]];
-          c1[u] = a.col_ptr[gi[u] + 1];
+        const int j = j0 + u * BLOCK;
+        if (j < v.np) {
+          r[u] = a.inv[v.lo + j];
+          f[u] = a.F[v.lo + j];
+          c0[u] = a.col_ptr[v.lo + j];
+          c1[u] = a.col_ptr[v.lo + j + 1];
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        if (i < v.np) {
-          v.Fq[i] = to_fixed((double)f[u] * inv_q);
-          v.dH[i] = 0.f;
-          v.lptr[i] = lp[u] - v.lbase;
-          v.odeg[i] = c1[u] - c0[u];
+        if (j0 + u * BLOCK < v.np) {
+          v.Fq[r[u]] = to_fixed((double)f[u] * inv_q);
+          v.dH[r[u]] = 0.f;
+          v.odeg[r[u]] = c1[u] - c0[u];
         }
       }
     }
@@ -305,60 +296,62 @@ __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
   __syncthreads();
 }
 
-// Sums of heavy items: rows with more than kPartHeavy external in-links are cut
-// in items of at most kItem links. Eight lanes sum a short item (at most 64
-// links, 8 per lane), a whole wave a long one; every lane has its gathers in
-// flight together. The sum is stored, then, when resident, the item's epoch
-// flag. The work units (8 short items, or one long item) are spread
-// round-robin over all waves of the grid, so a hub's inflow is summed by many
-// workgroups at once.
+// Sums of heavy items. Rows with more than kPartHeavy external in-links are
+// cut in items of at most kItem links. An item is summed by a group of 1..64
+// lanes (a power of two, eight links per lane); the plan packs the groups,
+// largest first and aligned to their size, into work units of one wave, and
+// stores for each unit the sources of every lane's eight slots, so a lane
+// loads them from one table row and a butterfly over its group adds them. The
+// group leader stores the sum as FP32 bits together with the level's epoch in
+// one 64-bit word. Units are spread round-robin over all waves of the grid, so
+// a hub's inflow is summed by many workgroups at once.
+struct UnitLane {
+  int32_t src[8];
+  int meta;
+};
+
+__device__ __forceinline__ void unit_load(const PartArgs& a, int64_t u, UnitLane& L) {
+  const int lane = threadIdx.x & 63;
+  const int32_t* t = a.unit_src + (size_t)u * 512 + lane;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) L.src[q] = t[64 * q];
+  L.meta = a.unit_meta[(size_t)u * 64 + lane];
+}
+
+// the whole wave calls this (the butterfly shuffles over all 64 lanes)
+template <bool RESIDENT>
+__device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, const UnitLane& L,
+                                         int epoch) {
+  float v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    v[q] = L.src[q] >= 0 ? (RESIDENT ? ld_agent(&S_in[L.src[q]]) : S_in[L.src[q]]) : 0.f;
+  double x = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) x += (double)v[q];
+  const int lanes = 1 << (L.meta & 7);
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    const double y = __shfl_xor(x, m, 64);
+    if (m < lanes) x += y;
+  }
+  const int item = (L.meta >> 3) - 1;
+  if (item >= 0) {
+    const unsigned long long w =
+        ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint((float)x);
+    if (RESIDENT) __hip_atomic_store(&a.item_word[item], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else a.item_word[item] = w;
+  }
+}
+
+// units first_wave, first_wave + n_waves, ... (the caller's wave)
 template <bool RESIDENT>
 __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first_wave, int64_t n_waves,
                           int epoch) {
-  const int lane = threadIdx.x & 63;
-  auto S = [&](int32_t i) { return RESIDENT ? ld_agent(&S_in[i]) : S_in[i]; };
-  auto store = [&](int64_t k, double x) {
-    if (RESIDENT) {
-      st_agent(&a.item_sum[k], x);
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // the sum lands before the flag
-      st_agent(&a.item_flag[k], epoch);
-    } else {
-      a.item_sum[k] = x;
-    }
-  };
-  const int64_t w_short = (a.n_short + 7) / 8;
-  for (int64_t w = first_wave; w < w_short + a.n_long; w += n_waves) {
-    if (w < w_short) {
-      const int64_t j = w * 8 + (lane >> 3);
-      const bool on = j < a.n_short;
-      const int64_t k = on ? a.short_items[j] : 0;
-      double x = 0;
-      if (on) {
-        const int32_t e0 = a.item_beg[k] + (lane & 7), e1 = a.item_end[k];
-        int32_t src[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) src[q] = e0 + 8 * q < e1 ? a.heavy_src[e0 + 8 * q] : -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (src[q] >= 0) x += (double)S(src[q]);
-      }
-      x += __shfl_xor(x, 1, 64);
-      x += __shfl_xor(x, 2, 64);
-      x += __shfl_xor(x, 4, 64);
-      if (on && (lane & 7) == 0) store(k, x);
-    } else {
-      const int64_t k = a.long_items[w - w_short];
-      const int32_t e0 = a.item_beg[k] + lane, e1 = a.item_end[k];
-      int32_t src[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) src[q] = e0 + 64 * q < e1 ? a.heavy_src[e0 + 64 * q] : -1;
-      double x = 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (src[q] >= 0) x += (double)S(src[q]);
-      x = wave_sum(x);
-      if (lane == 0) store(k, x);
-    }
+  for (int64_t u = first_wave; u < a.n_units; u += n_waves) {
+    UnitLane L;
+    unit_load(a, u, L);
+    unit_sum<RESIDENT>(a, S_in, L, epoch);
   }
 }
 
@@ -374,39 +367,59 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
                             int epoch, int spin_limit) {
   const int tid = threadIdx.x;
   auto ld = [&](int32_t s) { return RESIDENT ? ld_agent(&S_in[s]) : S_in[s]; };
-  const int e0 = a.ext_ptr[p], e1 = a.ext_ptr[p + 1];
-  int e = e0 + tid;
-  for (; e + 3 * BLOCK < e1; e += 4 * BLOCK) {  // four gathers in flight
-    const int32_t s0 = a.ext_src[e], s1 = a.ext_src[e + BLOCK], s2 = a.ext_src[e + 2 * BLOCK],
-                  s3 = a.ext_src[e + 3 * BLOCK];
-    const uint16_t r0 = a.ext_row[e], r1 = a.ext_row[e + BLOCK], r2 = a.ext_row[e + 2 * BLOCK],
-                   r3 = a.ext_row[e + 3 * BLOCK];
-    const float v0 = ld(s0), v1 = ld(s1), v2 = ld(s2), v3 = ld(s3);
-    if (v0 != 0.f) add_fixed(&v.Fq[r0], to_fixed((double)v0 * inv_q));
-    if (v1 != 0.f) add_fixed(&v.Fq[r1], to_fixed((double)v1 * inv_q));
-    if (v2 != 0.f) add_fixed(&v.Fq[r2], to_fixed((double)v2 * inv_q));
-    if (v3 != 0.f) add_fixed(&v.Fq[r3], to_fixed((double)v3 * inv_q));
-  }
-  for (; e < e1; e += BLOCK) {
-    const float x = ld(a.ext_src[e]);
-    if (x != 0.f) add_fixed(&v.Fq[a.ext_row[e]], to_fixed((double)x * inv_q));
+  const int e1 = a.ext_ptr[p + 1];
+  constexpr int U = 8;  // eight gathers in flight per thread
+  for (int e = a.ext_ptr[p] + tid; e < e1; e += U * BLOCK) {
+    int32_t src[U];
+    int r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool on = e + u * BLOCK < e1;
+      src[u] = on ? a.ext_src[e + u * BLOCK] : -1;
+      r[u] = on ? a.ext_row[e + u * BLOCK] : 0;
+    }
+    float x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = src[u] >= 0 ? ld(src[u]) : 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (x[u] != 0.f) add_fixed(&v.Fq[r[u]], to_fixed((double)x[u] * inv_q));
   }
   bool ok = true;
-  for (int k = a.part_items[p] + tid; k < a.part_items[p + 1]; k += BLOCK) {
-    if (RESIDENT) {
-      int spins = 0;
-      while (ld_agent(&a.item_flag[k]) != epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > spin_limit) {
-          ok = false;
-          __hip_atomic_store(&a.ctrl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+  const int k1 = a.part_items[p + 1];
+  constexpr int UI = 4;  // the first polls of four items in flight together
+  for (int k0 = a.part_items[p] + tid; k0 < k1 && ok; k0 += UI * BLOCK) {
+    int row[UI];
+    unsigned long long w[UI];
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int k = k0 + u * BLOCK;
+      if (k < k1) {
+        row[u] = a.item_row[k];
+        w[u] = RESIDENT ? __hip_atomic_load(&a.item_word[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : a.item_word[k];
       }
-      if (!ok) break;
     }
-    const double x = RESIDENT ? ld_agent(&a.item_sum[k]) : a.item_sum[k];
-    if (x != 0.0) add_fixed(&v.Fq[a.item_row[k]], to_fixed(x * inv_q));
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+      const int k = k0 + u * BLOCK;
+      if (k >= k1 || !ok) continue;
+      if (RESIDENT) {
+        int spins = 0;
+        while ((w[u] >> 32) != (unsigned long long)(unsigned)epoch) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > spin_limit) {
+            ok = false;
+            __hip_atomic_store(&a.ctrl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          w[u] = __hip_atomic_load(&a.item_word[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!ok) continue;
+      }
+      const float x = __uint_as_float((unsigned)w[u]);
+      if (x != 0.f) add_fixed(&v.Fq[row[u]], to_fixed((double)x * inv_q));
+    }
   }
   return __syncthreads_and(ok) != 0;
 }
@@ -454,6 +467,51 @@ __device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum
                             double& diffs) {
   if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, quantum, edges, diffs);
   else part_sweeps_t<BLOCK, false>(a, v, quantum, edges, diffs);
+}
+
+// 4. H += dH and the shares p_i dH_i published for the outside targets, in node
+// order through inv (H, S and F move coalesced; eight nodes per thread in
+// flight). Sums |F| plus the fluid in flight to outside targets into resid and
+// the largest |F| into fmx. RESIDENT: F stays in LDS and dH restarts from zero;
+// otherwise F goes back to memory.
+template <int BLOCK, bool RESIDENT>
+__device__ void part_publish(const PartArgs& a, const PartView& v, double quantum, float* S_out,
+                             double& resid, double& fmx) {
+  constexpr int U = 8;
+  for (int j0 = threadIdx.x; j0 < v.np; j0 += U * BLOCK) {
+    int r[U];
+    double hv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * BLOCK;
+      r[u] = j < v.np ? a.inv[v.lo + j] : 0;
+      hv[u] = j < v.np ? a.H[v.lo + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * BLOCK;
+      if (j >= v.np) continue;
+      const int i = r[u];
+      const int32_t g = v.lo + j;
+      const double f = (double)v.Fq[i] * quantum;
+      const double dh = (double)v.dH[i];
+      if (!RESIDENT) a.F[g] = (float)f;
+      float so = 0.f;
+      if (dh != 0.0) {
+        a.H[g] = hv[u] + dh;
+        if (RESIDENT) v.dH[i] = 0.f;
+        const int od = v.odeg[i];
+        if (od > 0) {
+          so = (float)(a.dd * dh / (double)od);
+          resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
+        }
+      }
+      if (RESIDENT) st_agent(&S_out[g], so);
+      else S_out[g] = so;
+      resid += fabs(f);
+      fmx = fmax(fmx, fabs(f));
+    }
+  }
 }
 
 // block-wide sums of (resid, edges, diffs) and max of fmx, in a fixed order;
@@ -519,44 +577,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
 
   // ---- 4. write back, publish p_i dH_i, partial sums
   double resid = 0, fmx = 0;
-  {
-    constexpr int U = 4;
-    for (int i0 = tid; i0 < v.np; i0 += U * BLOCK) {
-      int32_t gi[U];
-      double hv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        gi[u] = i < v.np ? v.lo + a.order[v.lo + i] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        hv[u] = (i < v.np && v.dH[i] != 0.f) ? a.H[gi[u]] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * BLOCK;
-        if (i >= v.np) continue;
-        const double f = (double)v.Fq[i] * quantum;
-        const double dh = (double)v.dH[i];
-        a.F[gi[u]] = (float)f;
-        float so = 0.f;
-        if (dh != 0.0) {
-          a.H[gi[u]] = hv[u] + dh;
-          const int od = v.odeg[i];
-          if (od > 0) {
-            so = (float)(a.dd * dh / (double)od);
-            // in flight to the outside targets of i
-            resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
-          }
-        }
-        S_out[gi[u]] = so;
-        resid += fabs(f);
-        fmx = fmax(fmx, fabs(f));
-      }
-    }
-  }
+  part_publish<BLOCK, false>(a, v, quantum, S_out, resid, fmx);
 
   // ---- 5. per-workgroup sums; the last workgroup finishes the launch
   block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
@@ -665,34 +686,22 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
 
   double quantum = fixed_quantum(T);
   part_load<BLOCK>(a, v, 1.0 / quantum);
+  // the wave's first item unit stays in registers for the whole launch
+  const int64_t unit0 = (int64_t)p * NW + (tid >> 6), n_waves = (int64_t)a.K * NW;
+  UnitLane L0;
+  if (unit0 < a.n_units) unit_load(a, unit0, L0);
   for (; levels < a.max_levels; ++levels) {
     const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
     float* S_out = a.S + (size_t)parity * a.n;
-    item_sums<true>(a, S_in, (int64_t)p * NW + (tid >> 6), (int64_t)a.K * NW, a.epoch0 + levels);
+    if (unit0 < a.n_units) unit_sum<true>(a, S_in, L0, a.epoch0 + levels);
+    item_sums<true>(a, S_in, unit0 + n_waves, n_waves, a.epoch0 + levels);
     if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, a.epoch0 + levels, spin_limit)) return;
     double edges = 0, diffs = 0;
     part_sweeps<BLOCK>(a, v, quantum, edges, diffs);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
     double resid = 0, fmx = 0;
-    for (int i = tid; i < v.np; i += BLOCK) {
-      const int32_t gi = v.lo + a.order[v.lo + i];
-      const double f = (double)v.Fq[i] * quantum;
-      const double dh = (double)v.dH[i];
-      float so = 0.f;
-      if (dh != 0.0) {
-        a.H[gi] += dh;
-        v.dH[i] = 0.f;
-        const int od = v.odeg[i];
-        if (od > 0) {
-          so = (float)(a.dd * dh / (double)od);
-          resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
-        }
-      }
-      st_agent(&S_out[gi], so);
-      resid += fabs(f);
-      fmx = fmax(fmx, fabs(f));
-    }
+    part_publish<BLOCK, true>(a, v, quantum, S_out, resid, fmx);
     // per-workgroup sums and the abort vote go to the slots of this level's
     // parity: a workgroup can reach the next level's publish while another
     // still reads this level's slots, never the one after
@@ -745,7 +754,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     quantum = qn;
     parity ^= 1;
   }
-  for (int i = tid; i < v.np; i += BLOCK) a.F[v.lo + a.order[v.lo + i]] = (float)((double)v.Fq[i] * quantum);
+  for (int j = tid; j < v.np; j += BLOCK) a.F[v.lo + j] = (float)((double)v.Fq[a.inv[v.lo + j]] * quantum);
   if (p == 0 && tid == 0) {
     a.ctrl->T = T;
     a.ctrl->done = done;
@@ -777,10 +786,9 @@ void free_part_plan(ditr_graph* g) {
   PartPlan& q = g->pp;
   for (void* p : {(void*)q.pid, (void*)q.loc_ptr, (void*)q.loc_idx, (void*)q.pw, (void*)q.ext_deg,
                   (void*)q.ext_ptr, (void*)q.ext_src, (void*)q.ext_row, (void*)q.heavy_rows,
-                  (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.item_row, (void*)q.item_beg,
-                  (void*)q.item_end, (void*)q.part_items, (void*)q.item_sum, (void*)q.item_flag,
-                  (void*)q.short_items, (void*)q.long_items,
-                  (void*)q.S, (void*)q.partials, (void*)q.counters, (void*)q.order})
+                  (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.item_row, (void*)q.part_items,
+                  (void*)q.unit_src, (void*)q.unit_meta, (void*)q.item_word,
+                  (void*)q.S, (void*)q.partials, (void*)q.counters, (void*)q.inv})
     (void)hipFree(p);
   q = PartPlan();
 }
@@ -885,26 +893,62 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     }
     pit[K] = (int32_t)irow.size();
     q.n_items = (int32_t)irow.size();
-    std::vector<int32_t> sh, lg;
-    for (int32_t k = 0; k < q.n_items; ++k) (iend[k] - ibeg[k] <= 64 ? sh : lg).push_back(k);
-    q.n_short = (int32_t)sh.size();
-    q.n_long = (int32_t)lg.size();
+    if (q.n_items >= (1 << 27)) {
+      cleanup();
+      return set_error(DITR_EINVAL, "too many heavy items (%d)", q.n_items);
+    }
+    // work units: an item takes a group of 2^l lanes, the fewest whose eight
+    // slots hold its links; groups are packed largest first, so each starts at
+    // a multiple of its size inside its unit
+    std::vector<int32_t> hsrc(std::max(1, nheavy_e));
+    if (nheavy_e > 0) PP_TRY(hipMemcpy(hsrc.data(), q.heavy_src, sizeof(int32_t) * nheavy_e, hipMemcpyDeviceToHost));
+    const int32_t ni = q.n_items;
+    std::vector<int> lg2(ni);
+    for (int32_t k = 0; k < ni; ++k) {
+      int l = 0;
+      while ((8 << l) < iend[k] - ibeg[k]) ++l;
+      lg2[k] = l;
+    }
+    std::vector<int32_t> by(ni);
+    for (int32_t k = 0; k < ni; ++k) by[k] = k;
+    std::stable_sort(by.begin(), by.end(), [&](int32_t x, int32_t y) { return lg2[x] > lg2[y]; });
+    std::vector<int32_t> usrc, umeta;
+    int lane = 64;
+    int64_t nu = 0;
+    for (int32_t k : by) {
+      const int gl = 1 << lg2[k];
+      if (lane + gl > 64) {
+        ++nu;
+        usrc.resize((size_t)nu * 512, -1);
+        umeta.resize((size_t)nu * 64, 0);
+        lane = 0;
+      }
+      const size_t u = (size_t)nu - 1;
+      for (int l = 0; l < gl; ++l) {
+        umeta[u * 64 + lane + l] = ((l == 0 ? k + 1 : 0) << 3) | lg2[k];
+        for (int qq = 0; qq < 8; ++qq) {
+          const int32_t e = ibeg[k] + l + gl * qq;
+          usrc[u * 512 + (size_t)qq * 64 + lane + l] = e < iend[k] ? hsrc[e] : -1;
+        }
+      }
+      lane += gl;
+    }
+    q.n_units = (int32_t)nu;
     auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
       HIP_TRY(hipMalloc((void**)dst, sizeof(int32_t) * std::max<size_t>(1, v.size())));
       if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
       return DITR_OK;
     };
     int urc = up(&q.item_row, irow);
-    if (!urc) urc = up(&q.item_beg, ibeg);
-    if (!urc) urc = up(&q.item_end, iend);
     if (!urc) urc = up(&q.part_items, pit);
-    if (!urc) urc = up(&q.short_items, sh);
-    if (!urc) urc = up(&q.long_items, lg);
+    if (!urc) urc = up(&q.unit_src, usrc);
+    if (!urc) urc = up(&q.unit_meta, umeta);
     if (urc) { cleanup(); return urc; }
-    PP_TRY(hipMalloc((void**)&q.item_sum, sizeof(double) * std::max<size_t>(1, irow.size())));
-    PP_TRY(hipMalloc((void**)&q.item_flag, sizeof(int) * std::max<size_t>(1, irow.size())));
-    PP_TRY(hipMemset(q.item_sum, 0, sizeof(double) * std::max<size_t>(1, irow.size())));
-    PP_TRY(hipMemset(q.item_flag, 0, sizeof(int) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMalloc((void**)&q.item_word, sizeof(unsigned long long) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMemset(q.item_word, 0, sizeof(unsigned long long) * std::max<size_t>(1, irow.size())));
+    // the unit table replaces the per-row source list
+    PP_TRY(hipFree(q.heavy_src));
+    q.heavy_src = nullptr;
   }
   q.n_heavy = nh;
   PP_TRY(hipMalloc((void**)&q.part_heavy, sizeof(int32_t) * (K + 1)));
@@ -949,8 +993,6 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
       for (int32_t b = 1; b <= dmax + 1; ++b) cnt[b] += cnt[b - 1];
       for (int64_t i = lo; i < hi; ++i) ord[lo + cnt[dmax - (lp[i + 1] - lp[i])]++] = (uint16_t)(i - lo);
     }
-    PP_TRY(hipMalloc((void**)&q.order, sizeof(uint16_t) * std::max<int64_t>(1, n)));
-    PP_TRY(hipMemcpy(q.order, ord.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
     // renumber each partition's nodes by that order: local id r is node
     // lo + order[lo + r]; the local CSC, the rows of the light external links
     // and the rows of the heavy items take the new ids
@@ -959,6 +1001,8 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
       const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
       for (int64_t r = 0; r < hi - lo; ++r) inv[lo + ord[lo + r]] = (uint16_t)r;
     }
+    PP_TRY(hipMalloc((void**)&q.inv, sizeof(uint16_t) * std::max<int64_t>(1, n)));
+    PP_TRY(hipMemcpy(q.inv, inv.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
     {
       std::vector<uint16_t> li((size_t)nloc + 4), li2((size_t)nloc + 4, 0);
       PP_TRY(hipMemcpy(li.data(), q.loc_idx, sizeof(uint16_t) * nloc, hipMemcpyDeviceToHost));
@@ -1058,24 +1102,19 @@ int part_args(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alph
   a.col_ptr = g->col_ptr;
   a.loc_ptr = q.loc_ptr;
   a.loc_idx = q.loc_idx;
-  a.order = q.order;
+  a.inv = q.inv;
   a.pw = q.pw;
   a.ext_deg = q.ext_deg;
   a.ext_ptr = q.ext_ptr;
   a.ext_src = q.ext_src;
   a.ext_row = q.ext_row;
-  a.heavy_src = q.heavy_src;
   a.part_items = q.part_items;
   a.item_row = q.item_row;
-  a.item_beg = q.item_beg;
-  a.item_end = q.item_end;
-  a.item_sum = q.item_sum;
-  a.item_flag = q.item_flag;
-  a.short_items = q.short_items;
-  a.long_items = q.long_items;
+  a.unit_src = q.unit_src;
+  a.unit_meta = q.unit_meta;
+  a.item_word = q.item_word;
   a.n_items = q.n_items;
-  a.n_short = q.n_short;
-  a.n_long = q.n_long;
+  a.n_units = q.n_units;
   a.epoch0 = 0;
   a.F = f;
   a.H = h;
@@ -1110,7 +1149,7 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   if (rc) return rc;
   const PartPlan& q = g->pp;
   for (int s = 0; s < nlaunch; ++s) {
-    const int64_t units = (q.n_short + 7) / 8 + q.n_long;
+    const int64_t units = q.n_units;
     if (units > 0)
       k_part_items<<<(unsigned)std::min<int64_t>((units + 3) / 4, 16384), 256, 0, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s], c->stream));
@@ -1148,7 +1187,7 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, 
   // epochs of this launch's levels: above every flag an earlier launch stored
   const PartPlan& q = g->pp;
   if ((int64_t)q.epoch + max_levels + 1 >= (int64_t)1 << 30) {  // restart the epochs
-    HIP_TRY(hipMemsetAsync(q.item_flag, 0, sizeof(int) * std::max(1, q.n_items), c->stream));
+    HIP_TRY(hipMemsetAsync(q.item_word, 0, sizeof(unsigned long long) * std::max(1, q.n_items), c->stream));
     const_cast<PartPlan&>(q).epoch = 0;
   }
   a.epoch0 = q.epoch + 1;
