@@ -344,11 +344,11 @@ __device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, c
   }
 }
 
-// units first_wave, first_wave + n_waves, ... (the caller's wave)
+// units first, first + stride, ... (the caller's wave)
 template <bool RESIDENT>
-__device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first_wave, int64_t n_waves,
+__device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first, int64_t stride,
                           int epoch) {
-  for (int64_t u = first_wave; u < a.n_units; u += n_waves) {
+  for (int64_t u = first; u < a.n_units; u += stride) {
     UnitLane L;
     unit_load(a, u, L);
     unit_sum<RESIDENT>(a, S_in, L, epoch);
@@ -544,7 +544,7 @@ __device__ void block_reduce4(double& r0, double& r1, double& r2, double& r3, do
 // Heavy-item sums as their own kernel, right before a launch of the sweep.
 __global__ void __launch_bounds__(256) k_part_items(PartArgs a, int parity) {
   if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  item_sums<false>(a, a.S + (size_t)(parity ^ 1) * a.n, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6),
+  item_sums<false>(a, a.S + (size_t)(parity ^ 1) * a.n, (int64_t)(threadIdx.x >> 6) * gridDim.x + blockIdx.x,
                    (int64_t)gridDim.x * 4, 0);
 }
 
@@ -686,8 +686,10 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
 
   double quantum = fixed_quantum(T);
   part_load<BLOCK>(a, v, 1.0 / quantum);
-  // the wave's first item unit stays in registers for the whole launch
-  const int64_t unit0 = (int64_t)p * NW + (tid >> 6), n_waves = (int64_t)a.K * NW;
+  // the wave's first item unit stays in registers for the whole launch; wave w
+  // of workgroup p takes units w K + p, (w + NW) K + p, ..., so the densest
+  // units (packed first) are spread over all CUs
+  const int64_t unit0 = (int64_t)(tid >> 6) * a.K + p, n_waves = (int64_t)a.K * NW;
   UnitLane L0;
   if (unit0 < a.n_units) unit_load(a, unit0, L0);
   for (; levels < a.max_levels; ++levels) {
