@@ -318,14 +318,17 @@ __device__ __forceinline__ void unit_load(const PartArgs& a, int64_t u, UnitLane
   L.meta = a.unit_meta[(size_t)u * 64 + lane];
 }
 
-// the whole wave calls this (the butterfly shuffles over all 64 lanes)
 template <bool RESIDENT>
-__device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, const UnitLane& L,
-                                         int epoch) {
-  float v[8];
+__device__ __forceinline__ void unit_gather(const float* S_in, const UnitLane& L, float (&v)[8]) {
 #pragma unroll
   for (int q = 0; q < 8; ++q)
     v[q] = L.src[q] >= 0 ? (RESIDENT ? ld_agent(&S_in[L.src[q]]) : S_in[L.src[q]]) : 0.f;
+}
+
+// the whole wave calls this (the butterfly shuffles over all 64 lanes)
+template <bool RESIDENT>
+__device__ __forceinline__ void unit_finish(const PartArgs& a, const UnitLane& L, const float (&v)[8],
+                                            int epoch) {
   double x = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) x += (double)v[q];
@@ -344,6 +347,14 @@ __device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, c
   }
 }
 
+template <bool RESIDENT>
+__device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, const UnitLane& L,
+                                         int epoch) {
+  float v[8];
+  unit_gather<RESIDENT>(S_in, L, v);
+  unit_finish<RESIDENT>(a, L, v, epoch);
+}
+
 // units first, first + stride, ... (the caller's wave)
 template <bool RESIDENT>
 __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first, int64_t stride,
@@ -355,6 +366,42 @@ __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first, i
   }
 }
 
+// The resident sweep splits the light inflow: the first kLight links of each
+// thread (sources and rows held in registers) have their shares gathered at the
+// start of a level, so the loads are in flight during the first local sweep,
+// and are added after it; links beyond them take the plain loop.
+constexpr int kLight = 8;
+
+// rows go two to a register (local ids are 16-bit)
+__device__ __forceinline__ void light_prep(const PartArgs& a, int p, int32_t (&src)[kLight],
+                                           uint32_t (&row)[kLight / 2]) {
+  const int e0 = a.ext_ptr[p] + threadIdx.x, e1 = a.ext_ptr[p + 1];
+#pragma unroll
+  for (int u = 0; u < kLight; ++u) {
+    const int e = e0 + u * (int)blockDim.x;
+    src[u] = e < e1 ? a.ext_src[e] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kLight; u += 2) {
+    const int e = e0 + u * (int)blockDim.x;
+    const uint32_t r0 = e < e1 ? a.ext_row[e] : 0u;
+    const uint32_t r1 = e + (int)blockDim.x < e1 ? a.ext_row[e + blockDim.x] : 0u;
+    row[u / 2] = r0 | (r1 << 16);
+  }
+}
+
+__device__ __forceinline__ void light_gather(const float* S_in, const int32_t (&src)[kLight], float (&x)[kLight]) {
+#pragma unroll
+  for (int u = 0; u < kLight; ++u) x[u] = src[u] >= 0 ? ld_agent(&S_in[src[u]]) : 0.f;
+}
+
+__device__ __forceinline__ void light_apply(const PartView& v, const uint32_t (&row)[kLight / 2],
+                                            const float (&x)[kLight], double inv_q) {
+#pragma unroll
+  for (int u = 0; u < kLight; ++u)
+    if (x[u] != 0.f) add_fixed(&v.Fq[(row[u / 2] >> (16 * (u & 1))) & 0xFFFFu], to_fixed((double)x[u] * inv_q));
+}
+
 // 2. outside fluid, pulled by the partition that owns it: each light external
 // in-link (source, local row) adds the source's published share (one thread
 // per link, LDS atomics); each heavy item of the partition adds its sum
@@ -364,12 +411,12 @@ __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first, i
 // Returns false on a timed-out wait.
 template <int BLOCK, bool RESIDENT>
 __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const float* S_in, double inv_q,
-                            int epoch, int spin_limit) {
+                            int epoch, int spin_limit, int skip = 0) {
   const int tid = threadIdx.x;
   auto ld = [&](int32_t s) { return RESIDENT ? ld_agent(&S_in[s]) : S_in[s]; };
   const int e1 = a.ext_ptr[p + 1];
   constexpr int U = 8;  // eight gathers in flight per thread
-  for (int e = a.ext_ptr[p] + tid; e < e1; e += U * BLOCK) {
+  for (int e = a.ext_ptr[p] + skip * BLOCK + tid; e < e1; e += U * BLOCK) {
     int32_t src[U];
     int r[U];
 #pragma unroll
@@ -424,7 +471,7 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
   return __syncthreads_and(ok) != 0;
 }
 
-// 3. local threshold sweeps at one T until none passes (at most m). Each
+// 3. local threshold sweeps s0..s1-1 at one T until none passes. Each
 // thread takes one node at a time in local-id order (consecutive ids have about
 // the same local out-degree, so a wave's lanes finish their lists together)
 // and pushes its share to every local target with LDS atomics, eight targets
@@ -432,11 +479,11 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
 // a known address space and the loop waits on LDS traffic only).
 template <int BLOCK, bool TARGETS_LDS>
 __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quantum, double& edges,
-                              double& diffs) {
+                              double& diffs, int s0, int s1) {
   const uint16_t* __restrict__ lidx =
       TARGETS_LDS ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1) : a.loc_idx + v.lbase;
   const long long Tq = 1LL << 32;  // T in fixed point
-  for (int s = 0; s < a.m; ++s) {
+  for (int s = s0; s < s1; ++s) {
     int passed = 0;
     for (int i = threadIdx.x; i < v.np; i += BLOCK) {
       const long long f = v.Fq[i];
@@ -464,9 +511,9 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
 
 template <int BLOCK>
 __device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum, double& edges,
-                            double& diffs) {
-  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, quantum, edges, diffs);
-  else part_sweeps_t<BLOCK, false>(a, v, quantum, edges, diffs);
+                            double& diffs, int s0, int s1) {
+  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, quantum, edges, diffs, s0, s1);
+  else part_sweeps_t<BLOCK, false>(a, v, quantum, edges, diffs, s0, s1);
 }
 
 // 4. H += dH and the shares p_i dH_i published for the outside targets, in node
@@ -573,7 +620,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   part_load<BLOCK>(a, v, 1.0 / quantum);
   part_inflow<BLOCK, false>(a, v, p, S_in, 1.0 / quantum, 0, 0);
   double edges = 0, diffs = 0;
-  part_sweeps<BLOCK>(a, v, quantum, edges, diffs);
+  part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 0, a.m);
 
   // ---- 4. write back, publish p_i dH_i, partial sums
   double resid = 0, fmx = 0;
@@ -686,24 +733,38 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
 
   double quantum = fixed_quantum(T);
   part_load<BLOCK>(a, v, 1.0 / quantum);
-  // the wave's first item unit stays in registers for the whole launch; wave w
-  // of workgroup p takes units w K + p, (w + NW) K + p, ..., so the densest
-  // units (packed first) are spread over all CUs
+  // wave w of workgroup p takes item units w K + p, (w + NW) K + p, ..., so
+  // the densest units (packed first) are spread over all CUs; the sources of
+  // the first one and of the first light links are loaded at the end of the
+  // level before (they are constant), out of the register-heavy publish
   const int64_t unit0 = (int64_t)(tid >> 6) * a.K + p, n_waves = (int64_t)a.K * NW;
   UnitLane L0;
   if (unit0 < a.n_units) unit_load(a, unit0, L0);
+  int32_t lsrc[kLight];
+  uint32_t lrow[kLight / 2];
+  light_prep(a, p, lsrc, lrow);
   for (; levels < a.max_levels; ++levels) {
     const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
     float* S_out = a.S + (size_t)parity * a.n;
-    if (unit0 < a.n_units) unit_sum<true>(a, S_in, L0, a.epoch0 + levels);
-    item_sums<true>(a, S_in, unit0 + n_waves, n_waves, a.epoch0 + levels);
-    if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, a.epoch0 + levels, spin_limit)) return;
+    const int epoch = a.epoch0 + levels;
+    // the outside shares are gathered first and land during the first local
+    // sweep; they join the fluid before the second one
+    float iv[8], lv[kLight];
+    if (unit0 < a.n_units) unit_gather<true>(S_in, L0, iv);
+    light_gather(S_in, lsrc, lv);
     double edges = 0, diffs = 0;
-    part_sweeps<BLOCK>(a, v, quantum, edges, diffs);
+    part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 0, 1);
+    if (unit0 < a.n_units) unit_finish<true>(a, L0, iv, epoch);
+    item_sums<true>(a, S_in, unit0 + n_waves, n_waves, epoch);
+    light_apply(v, lrow, lv, 1.0 / quantum);
+    if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, epoch, spin_limit, kLight)) return;
+    part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 1, a.m);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
     double resid = 0, fmx = 0;
     part_publish<BLOCK, true>(a, v, quantum, S_out, resid, fmx);
+    if (unit0 < a.n_units) unit_load(a, unit0, L0);  // for the next level
+    light_prep(a, p, lsrc, lrow);
     // per-workgroup sums and the abort vote go to the slots of this level's
     // parity: a workgroup can reach the next level's publish while another
     // still reads this level's slots, never the one after
