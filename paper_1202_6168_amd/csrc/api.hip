@@ -473,8 +473,12 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     // FP32 fluid and its rounding drift; later stages aim below the target
     const double stage = (!refreshed && r > o.refresh_at * b1) ? std::max(target, o.refresh_at * b1)
                                                                : 0.5 * target;
-    // the threshold continues from the previous round (never above max|F| / alpha)
-    double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha) : fmax / o.alpha;
+    // the threshold continues from the previous round (never above max|F| / alpha);
+    // the first one starts at max|F| / alpha or at the mean |F| if lower, so a
+    // start whose fluid sits in a few large entries (a learned warm start)
+    // does not spend its first levels on those alone
+    double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha)
+                              : std::min(fmax / o.alpha, r / (double)std::max<int64_t>(1, g->n));
     if (mode == DITR_MODE_PARTITION) T0 = std::max(T0, r * kPartTFloor);
     rc = launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
