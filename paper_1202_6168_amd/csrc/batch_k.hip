@@ -24,6 +24,7 @@ constexpr int kBB = 256;          // threads per block (4 waves)
 constexpr int kMaxR = 256;        // right-hand sides per call (64 lanes x 4)
 constexpr int kFinBlocks = 256;   // blocks finishing the heavy rows of a refresh
 constexpr int kSub = 16;          // workgroups per heavy chunk (kHeavyChunk / kSub in-links each)
+constexpr int kStepBlocks = 64;   // workgroups of the per-sweep reduction
 
 struct BatchArgs {
   int64_t n;
@@ -44,11 +45,12 @@ struct BatchArgs {
   uint8_t* act;                    // [2][n] row of S nonzero
   float* heavy_in;                 // [n_heavy][R]
   double* racc;                    // [n_heavy][R] refresh accumulator of heavy rows
-  double* part;                    // [nblocks + kFinBlocks][R][2]: sum |fluid|, diffused edges
+  double* part;                    // [nblocks + kFinBlocks + kStepBlocks][R][2]: sum |fluid|, diffused edges
   double* T;                       // [R] thresholds
   double* tol;                     // [R] absolute targets
   int* done;                       // [R] 1 once the right-hand side met its target
   int* all_done;                   // all right-hand sides done
+  int* step_count;                 // workgroups of k_batch_step that finished (reset by the last)
   float d;                         // damping, FP32 fluid arithmetic
   double dd;                       // damping, FP64 exact residual
   int nblocks;
@@ -260,20 +262,45 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
 }
 
 // after a sweep: per right-hand side, fluid (held plus in flight and in the
-// heavy accumulators) and edges; stop test; T_r <- T_r / alpha
+// heavy accumulators) and edges; stop test; T_r <- T_r / alpha. kStepBlocks
+// workgroups each sum a slice of the sweep's block partials and of the heavy
+// rows for every right-hand side; the last one to finish adds the slices in a
+// fixed order and takes the decisions (its count is reset for the next sweep).
 __global__ void __launch_bounds__(kMaxR) k_batch_step(BatchArgs a, double alpha, double* resid_out,
                                                       double* edges_acc, unsigned long long* sweeps) {
   if (__hip_atomic_load(a.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  __shared__ int s_all;
-  if (threadIdx.x == 0) s_all = 1;
-  __syncthreads();
+  __shared__ int s_all, s_last;
+  const int G = gridDim.x, gb = blockIdx.x;
+  double* sp = a.part + (size_t)(a.nblocks + kFinBlocks) * a.R * 2;  // [G][R][2]
+  const int b0 = (int)((int64_t)a.nblocks * gb / G), b1 = (int)((int64_t)a.nblocks * (gb + 1) / G);
+  const int h0 = (int)((int64_t)a.n_heavy * gb / G), h1 = (int)((int64_t)a.n_heavy * (gb + 1) / G);
   for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
     double s = 0, e = 0;
-    for (int b = 0; b < a.nblocks; ++b) {
+    for (int b = b0; b < b1; ++b) {
       s += a.part[((size_t)b * a.R + r) * 2 + 0];
       e += a.part[((size_t)b * a.R + r) * 2 + 1];
     }
-    for (int h = 0; h < a.n_heavy; ++h) s += fabs((double)a.heavy_in[(size_t)h * a.R + r]);
+    for (int h = h0; h < h1; ++h) s += fabs((double)a.heavy_in[(size_t)h * a.R + r]);
+    st_agent(&sp[((size_t)gb * a.R + r) * 2 + 0], s);
+    st_agent(&sp[((size_t)gb * a.R + r) * 2 + 1], e);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // s_waitcnt vmcnt(0): the slice sums land first
+  __syncthreads();
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(a.step_count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == G - 1;
+  __syncthreads();
+  if (!s_last) return;
+  if (threadIdx.x == 0) {
+    s_all = 1;
+    __hip_atomic_store(a.step_count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
+    double s = 0, e = 0;
+    for (int q = 0; q < G; ++q) {
+      s += ld_agent(&sp[((size_t)q * a.R + r) * 2 + 0]);
+      e += ld_agent(&sp[((size_t)q * a.R + r) * 2 + 1]);
+    }
     resid_out[r] = s;
     edges_acc[r] += e;
     if (!a.done[r]) {
@@ -489,13 +516,13 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
   B_TRY(hipMalloc((void**)&w.heavy_in, sizeof(float) * std::max(1, g->n_heavy) * R));
   B_TRY(hipMalloc((void**)&w.racc, sizeof(double) * std::max(1, g->n_heavy) * R));
   B_TRY(hipMemsetAsync(w.racc, 0, sizeof(double) * std::max(1, g->n_heavy) * R, st));
-  B_TRY(hipMalloc((void**)&w.part, sizeof(double) * (nblocks + kFinBlocks) * R * 2));
-  B_TRY(hipMemsetAsync(w.part, 0, sizeof(double) * (nblocks + kFinBlocks) * R * 2, st));
+  B_TRY(hipMalloc((void**)&w.part, sizeof(double) * (nblocks + kFinBlocks + kStepBlocks) * R * 2));
+  B_TRY(hipMemsetAsync(w.part, 0, sizeof(double) * (nblocks + kFinBlocks + kStepBlocks) * R * 2, st));
   B_TRY(hipMalloc((void**)&w.lane, sizeof(double) * 5 * R));
-  B_TRY(hipMalloc((void**)&w.flags, sizeof(int) * (R + 2)));
+  B_TRY(hipMalloc((void**)&w.flags, sizeof(int) * (R + 3)));
   B_TRY(hipMalloc((void**)&w.sweeps, sizeof(unsigned long long)));
   B_TRY(hipMemsetAsync(w.lane, 0, sizeof(double) * 5 * R, st));
-  B_TRY(hipMemsetAsync(w.flags, 0, sizeof(int) * (R + 2), st));
+  B_TRY(hipMemsetAsync(w.flags, 0, sizeof(int) * (R + 3), st));
   B_TRY(hipMemsetAsync(w.sweeps, 0, sizeof(unsigned long long), st));
 
   BatchArgs a;
@@ -526,6 +553,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
   a.done = w.flags;
   a.all_done = w.flags + R;
   int* remaining = w.flags + R + 1;
+  a.step_count = w.flags + R + 2;
   a.d = (float)g->d;
   a.dd = g->d;
   a.nblocks = nblocks;
@@ -552,7 +580,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
   for (int s = 0; s < kBatchSweeps; ++s) {
     if (a.n_chunks > 0) k_batch_heavy<<<a.n_chunks * kSub, kBB, 0, st>>>(a, s & 1);
     k_batch_sweep<<<nblocks, kBB, 0, st>>>(a, s & 1);
-    k_batch_step<<<1, kMaxR, 0, st>>>(a, o.alpha, resid, edges, w.sweeps);
+    k_batch_step<<<kStepBlocks, kMaxR, 0, st>>>(a, o.alpha, resid, edges, w.sweeps);
   }
   hipError_t ce = hipStreamEndCapture(st, &graph);
   if (ce != hipSuccess) return fail(set_error(DITR_EHIP, "graph capture failed: %s", hipGetErrorString(ce)));
