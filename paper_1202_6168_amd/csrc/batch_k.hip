@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
       }
     }
     int any = 0;
+    float4 so = make_float4(0.f, 0.f, 0.f, 0.f);
     if (on) {
       const size_t o = (size_t)j * a.R + r0;
       const float4 f0 = *reinterpret_cast<const float4*>(&a.F[o]);
@@ -230,9 +231,10 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
         *reinterpret_cast<double2*>(&a.H[o]) = h01;
         *reinterpret_cast<double2*>(&a.H[o + 2]) = h23;
       }
-      *reinterpret_cast<float4*>(&a.F[o]) = make_float4(f[0], f[1], f[2], f[3]);
-      const float4 so = make_float4(s[0] * p, s[1] * p, s[2] * p, s[3] * p);
-      *reinterpret_cast<float4*>(&S_out[o]) = so;
+      // F is rewritten only where it changed
+      const bool inflow = (acc.x != 0.f) | (acc.y != 0.f) | (acc.z != 0.f) | (acc.w != 0.f);
+      if (sel || inflow) *reinterpret_cast<float4*>(&a.F[o]) = make_float4(f[0], f[1], f[2], f[3]);
+      so = make_float4(s[0] * p, s[1] * p, s[2] * p, s[3] * p);
       any = (so.x != 0.f) | (so.y != 0.f) | (so.z != 0.f) | (so.w != 0.f);
       for (int k = 0; k < 4; ++k) {
         resid[k] += fabs((double)f[k]) + (deg > 0 ? (double)a.d * fabs((double)s[k]) : 0.0);
@@ -240,6 +242,9 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
       }
     }
     any = __ballot(any) != 0ull;
+    // the S row is read only when some lane of it is active: then every lane
+    // writes its part; an inactive row keeps whatever it held
+    if (any && on) *reinterpret_cast<float4*>(&S_out[(size_t)j * a.R + r0]) = so;
     if (lane == 0) act_out[j] = (uint8_t)any;
   }
   // per-lane block sums
