@@ -168,6 +168,7 @@ int ditr_graph_destroy(ditr_graph* g) {
   (void)hipFree(g->chunk_h);
   (void)hipFree(g->chunk_beg);
   (void)hipFree(g->chunk_end);
+  (void)hipFree(g->chunk_sum);
   (void)hipFree(g->pull_s);
   (void)hipFree(g->pull_heavy);
   (void)hipFree(g->pull_partials);

@@ -91,6 +91,7 @@ struct ditr_graph {
   int32_t* chunk_beg = nullptr;      // heavy chunk -> first in-link (CSR position)
   int32_t* chunk_end = nullptr;      // heavy chunk -> one past its last in-link
   int32_t n_chunks = 0;
+  double* chunk_sum = nullptr;       // [n_chunks] exact-residual sum of one heavy chunk
   float* pull_s = nullptr;           // [2][n] sent fluid times p_ji of the previous / current sweep
   double* pull_heavy = nullptr;      // [2][n_heavy] chunked inflow of heavy rows
   double* pull_partials = nullptr;   // per-workgroup sums of one pull sweep

@@ -250,6 +250,7 @@ int build_heavy_chunks(ditr_ctx* c, ditr_graph* g) {
     HIP_TRY(hipMemcpy(g->chunk_beg, cb.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->chunk_end, ce.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
   }
+  HIP_TRY(hipMalloc((void**)&g->chunk_sum, sizeof(double) * nc));
   HIP_TRY(hipMalloc((void**)&g->pull_s, sizeof(float) * 2 * g->n));
   HIP_TRY(hipMalloc((void**)&g->pull_heavy, sizeof(double) * 2 * std::max(1, nh)));
   HIP_TRY(hipMalloc((void**)&g->pull_partials,

@@ -143,15 +143,36 @@ __global__ void k_refresh_wh(int64_t n, const int32_t* __restrict__ col_ptr,
   }
 }
 
-// 8 lanes per row for rows with in-degree <= kHeavyRow; heavy rows are skipped
-__global__ void __launch_bounds__(kRedBlock) k_refresh_light(
-    int64_t n, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ csr_col,
+// Exact residual B + P H - H: blocks [0, nl) take the rows with in-degree <=
+// kHeavyRow (8 lanes per row); blocks [nl, nl + n_chunks) sum one kHeavyChunk
+// piece of a heavy row each into chunk_sum
+__global__ void __launch_bounds__(kRedBlock) k_refresh_main(
+    int64_t n, int nl, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ csr_col,
     const double* __restrict__ wh, const double* __restrict__ b, const double* __restrict__ h,
-    float* __restrict__ f, double* partials) {
+    float* __restrict__ f, double* partials, const int32_t* __restrict__ chunk_beg,
+    const int32_t* __restrict__ chunk_end, double* __restrict__ chunk_sum) {
+  if ((int)blockIdx.x >= nl) {
+    // one kHeavyChunk piece of a heavy row: eight gathers in flight per thread
+    const int c = (int)blockIdx.x - nl;
+    const int32_t e1 = chunk_end[c];
+    double acc = 0, unused = 0, um = 0;
+    constexpr int U = 8;
+    for (int32_t e = chunk_beg[c] + threadIdx.x; e < e1; e += U * kRedBlock) {
+      int32_t i[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) i[u] = e + u * kRedBlock < e1 ? csr_col[e + u * kRedBlock] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i[u] >= 0) acc += wh[i[u]];
+    }
+    block_reduce3<kRedBlock>(acc, unused, um);
+    if (threadIdx.x == 0) chunk_sum[c] = acc;
+    return;
+  }
   const int sub = threadIdx.x & 7;
   double s = 0, unused = 0, m = 0;
   const int64_t rows_per_block = kRedBlock / 8;
-  for (int64_t base = blockIdx.x * rows_per_block; base < n; base += gridDim.x * rows_per_block) {
+  for (int64_t base = blockIdx.x * rows_per_block; base < n; base += (int64_t)nl * rows_per_block) {
     const int64_t j = base + (threadIdx.x >> 3);
     bool live = false;
     double acc = 0;
@@ -179,26 +200,27 @@ __global__ void __launch_bounds__(kRedBlock) k_refresh_light(
   }
 }
 
-// one workgroup per heavy row (block-stride over the heavy-row list)
-__global__ void __launch_bounds__(kRedBlock) k_refresh_heavy(
-    int32_t n_heavy, const int32_t* __restrict__ rows, const int32_t* __restrict__ row_ptr,
-    const int32_t* __restrict__ csr_col, const double* __restrict__ wh,
-    const double* __restrict__ b, const double* __restrict__ h, float* __restrict__ f,
-    double* partials) {
-  double s = 0, m = 0;
-  for (int32_t r = blockIdx.x; r < n_heavy; r += gridDim.x) {
-    const int32_t j = rows[r];
-    double acc = 0, unused = 0, um = 0;
-    for (int32_t e = row_ptr[j] + threadIdx.x; e < row_ptr[j + 1]; e += kRedBlock)
-      acc += wh[csr_col[e]];
-    block_reduce3<kRedBlock>(acc, unused, um);
-    if (threadIdx.x == 0) {
-      double v = b[j] - h[j] + acc;
-      f[j] = (float)v;
-      s += fabs(v);
-      m = fmax(m, fabs(v));
+// heavy rows: each thread adds the chunk sums of one row in chunk order
+__global__ void __launch_bounds__(kRedBlock) k_refresh_heavy_fin(
+    int32_t n_heavy, const int32_t* __restrict__ rows, const int32_t* __restrict__ chunk_h,
+    int32_t n_chunks, const double* __restrict__ chunk_sum, const double* __restrict__ b,
+    const double* __restrict__ h, float* __restrict__ f, double* partials) {
+  double s = 0, unused = 0, m = 0;
+  for (int32_t r = blockIdx.x * kRedBlock + threadIdx.x; r < n_heavy; r += gridDim.x * kRedBlock) {
+    int32_t lo = 0, hi = n_chunks;  // first chunk of row r
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (chunk_h[mid] < r) lo = mid + 1; else hi = mid;
     }
+    double acc = 0;
+    for (int32_t c = lo; c < n_chunks && chunk_h[c] == r; ++c) acc += chunk_sum[c];
+    const int32_t j = rows[r];
+    const double v = b[j] - h[j] + acc;
+    f[j] = (float)v;
+    s += fabs(v);
+    m = fmax(m, fabs(v));
   }
+  block_reduce3<kRedBlock>(s, unused, m);
   if (threadIdx.x == 0) {
     partials[kPartialStride * blockIdx.x + 0] = s;
     partials[kPartialStride * blockIdx.x + 1] = m;
@@ -630,19 +652,23 @@ int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const doub
   const int64_t n = g->n;
   k_refresh_wh<<<grid_for(n, 256, 8192), 256, 0, c->stream>>>(n, g->col_ptr, h, g->d, g->wh);
   HIP_TRY(hipGetLastError());
+  // light rows and the heavy chunks in one launch, then the heavy rows from
+  // their chunk sums (every sum in a fixed order)
   const int cap = (int)c->partials_cap;
-  int nh = g->n_heavy > 0 ? (g->n_heavy < cap / 4 ? g->n_heavy : cap / 4) : 0;
-  int nl = grid_for(n, kRedBlock / 8, cap - nh);
-  k_refresh_light<<<nl, kRedBlock, 0, c->stream>>>(n, g->row_ptr, g->csr_col, g->wh, b, h, f,
-                                                   c->partials);
+  const int nf = g->n_heavy > 0 ? std::min(64, (g->n_heavy + kRedBlock - 1) / kRedBlock) : 0;
+  const int nl = grid_for(n, kRedBlock / 8, cap - nf);
+  const int nc = g->n_heavy > 0 ? g->n_chunks : 0;
+  k_refresh_main<<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, g->wh, b, h, f,
+                                                       c->partials, g->chunk_beg, g->chunk_end,
+                                                       g->chunk_sum);
   HIP_TRY(hipGetLastError());
-  if (nh > 0) {
-    k_refresh_heavy<<<nh, kRedBlock, 0, c->stream>>>(g->n_heavy, g->heavy_rows, g->row_ptr,
-                                                     g->csr_col, g->wh, b, h, f,
-                                                     c->partials + kPartialStride * nl);
+  if (nf > 0) {
+    k_refresh_heavy_fin<<<nf, kRedBlock, 0, c->stream>>>(g->n_heavy, g->heavy_rows, g->chunk_h,
+                                                         g->n_chunks, g->chunk_sum, b, h, f,
+                                                         c->partials + kPartialStride * nl);
     HIP_TRY(hipGetLastError());
   }
-  return finalize_partials(c, nl + nh);
+  return finalize_partials(c, nl + nf);
 }
 
 template <int BLOCK>
