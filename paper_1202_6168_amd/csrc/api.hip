@@ -461,6 +461,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
 
   int status = DITR_OK;
   double t_carry = 0;
+  bool resident_ran = false;
   while (r > target) {
     if (st.rounds >= o.max_rounds) {
       status = DITR_NOT_CONVERGED;
@@ -496,7 +497,6 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       }
       if (resident) {
         // every partition resident for the whole stage: one cooperative launch
-        const uint64_t before = c->ctrl_host->sweeps;
         rc = t_begin();
         if (!rc) {
           rc = launch_part_resident(c, g, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30));
@@ -506,12 +506,14 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
             rc = DITR_OK;
           }
         }
+        // no readback here: the refresh below ends with one, which also
+        // carries the barrier-timeout flag of this launch
         if (!rc && resident) rc = t_end(1);
-        if (!rc && resident) rc = read_ctrl(c);
         if (rc) return finish(rc);
-        if (resident && c->ctrl_host->err == 2)
-          return finish(set_error(DITR_EHIP, "a grid barrier of the resident sweep timed out"));
-        if (resident) st.launches += 1;
+        if (resident) {
+          st.launches += 1;
+          resident_ran = true;
+        }
       }
       // otherwise launches of m local sweeps in batches; the stop flag turns the
       // rest of a batch into no-ops
@@ -553,6 +555,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     rc = launch_refresh(c, g, d_b, d_h, d_f);
     if (!rc) rc = read_ctrl(c);
     if (rc) return finish(rc);
+    if (resident_ran && c->ctrl_host->err == 2)
+      return finish(set_error(DITR_EHIP, "a grid barrier of the resident sweep timed out"));
     st.refreshes += 1;
     st.rounds += 1;
     refreshed = true;
