@@ -195,6 +195,78 @@ def test_headline_resident_and_relaunch(ctx, headline, flags):
     assert (st.launches <= st.rounds) if flags == 0 else (st.launches >= st.sweeps)
 
 
+def uniform_graph(n, outdeg, seed, dangling=0.1):
+    """Seeded graph: every non-dangling node has `outdeg` targets drawn
+    uniformly (repeated links and self-loops allowed)."""
+    rng = np.random.default_rng(seed)
+    deg = np.where(rng.random(n) < dangling, 0, outdeg).astype(np.int64)
+    cp = np.zeros(n + 1, np.int64)
+    cp[1:] = np.cumsum(deg)
+    ri = rng.integers(0, n, int(cp[-1]))
+    return cp.astype(np.int32), ri.astype(np.int32)
+
+
+def plan_counts(cp, ri, omega, heavy=4, item=512):
+    """Per partition, the light outside in-links (rows with at most `heavy` of
+    them) and, overall, the one-wave work units of the heavy items (a row's
+    outside in-links cut in items of at most `item`; an item takes 2^l lanes of
+    eight links; 64 lanes per unit, packed without gaps largest first)."""
+    n = cp.size - 1
+    pid = np.searchsorted(omega, np.arange(n), side="right") - 1
+    src = np.repeat(np.arange(n), np.diff(cp))
+    ext = pid[src] != pid[ri]
+    extin = np.bincount(ri[ext], minlength=n)
+    light = extin <= heavy
+    light_per_part = np.bincount(pid[light], weights=extin[light], minlength=omega.size - 1)
+    c = extin[~light].astype(np.int64)
+    full = (c - 1) // item                      # items of `item` links: 64 lanes each
+    last = c - full * item                      # the last item of each row
+    lanes = full * 64 + 2 ** np.ceil(np.log2(np.ceil(last / 8))).astype(np.int64)
+    return light_per_part, int(np.ceil(lanes.sum() / 64))
+
+
+def partitions_of(ctx, cp, ri, **opt):
+    g = ditr.Graph(ctx, *upload(cp, ri), opts=ditr.opts_default(**opt))
+    omega = np.asarray(g.partitions(), np.int64)
+    g.close()
+    return omega
+
+
+@pytest.mark.parametrize("flags", [0, ditr.FLAG_NO_RESIDENT])
+def test_more_item_units_than_waves(ctx, flags):
+    """Nearly every row of a uniform random graph has more than four outside
+    in-links, so the heavy items fill more one-wave work units than the
+    resident grid has waves: each wave then sums several units per level."""
+    n, pn = 300_000, 4700
+    cp, ri = uniform_graph(n, 10, seed=5)
+    omega = partitions_of(ctx, cp, ri, part_nodes=pn)
+    K = omega.size - 1
+    _, units = plan_counts(cp, ri, omega)
+    assert units > 3 * K * 16  # 16 waves per 1024-thread workgroup
+    b = np.full(n, 0.15 / n)
+    ref = oracle.solve(cp, ri, b, rel_tol=1e-13)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-10, mode=ditr.MODE_PARTITION, part_nodes=pn, flags=flags)
+    check_parity(cp, ri, b, h, f, st, 1e-10, ref=ref)
+    assert (st.launches <= st.rounds) if flags == 0 else (st.launches >= st.sweeps)
+
+
+@pytest.mark.parametrize("flags", [0, ditr.FLAG_NO_RESIDENT])
+def test_light_links_beyond_the_register_batch(ctx, flags):
+    """Two partitions of 6000 nodes with ~2 light outside in-links per row:
+    over 8192 light links per partition, more than the eight per thread the
+    resident sweep gathers during its first local sweep; the rest take the
+    plain loop after it."""
+    n, pn = 12_000, 6000
+    cp, ri = uniform_graph(n, 4, seed=8)
+    omega = partitions_of(ctx, cp, ri, part_nodes=pn)
+    light, _ = plan_counts(cp, ri, omega)
+    assert omega.size - 1 == 2 and light.min() > 8 * 1024
+    b = np.random.default_rng(3).uniform(0.1, 1.0, n) / n
+    ref = oracle.solve(cp, ri, b, rel_tol=1e-14)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-11, mode=ditr.MODE_PARTITION, part_nodes=pn, flags=flags)
+    check_parity(cp, ri, b, h, f, st, 1e-11, ref=ref, ref_tol=1e-14)
+
+
 def test_repeat_runs_within_parity(ctx, headline):
     """Runs may differ (float atomics); every run must stay within parity."""
     cp, ri, b, ref = headline
