@@ -41,6 +41,8 @@ struct BatchArgs {
   const double* B;                 // [n][R]
   float* F;                        // [n][R]
   double* H;                       // [n][R]
+  float* G;                        // [n][R] history increments of the current stage (FP32),
+                                   //   added into H before each exact refresh
   float* S;                        // [2][n][R]
   uint8_t* act;                    // [2][n] row of S nonzero
   float* heavy_in;                 // [n_heavy][R]
@@ -65,7 +67,7 @@ __device__ __forceinline__ int find_row(const int32_t* rows, int nh, int j) {
   return lo;
 }
 
-// init: F = (float)B, H = 0, S = 0, activity = 0; per block sum |B| and max |B| per lane
+// init: F = (float)B, H = 0, G = 0, S = 0, activity = 0; per block sum |B| and max |B| per lane
 __global__ void __launch_bounds__(kBB) k_batch_init(BatchArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nw = (int64_t)gridDim.x * (kBB / 64);
@@ -80,6 +82,7 @@ __global__ void __launch_bounds__(kBB) k_batch_init(BatchArgs a) {
       *reinterpret_cast<float4*>(&a.F[o]) = f;
       *reinterpret_cast<double2*>(&a.H[o]) = make_double2(0.0, 0.0);
       *reinterpret_cast<double2*>(&a.H[o + 2]) = make_double2(0.0, 0.0);
+      *reinterpret_cast<float4*>(&a.G[o]) = make_float4(0.f, 0.f, 0.f, 0.f);
       *reinterpret_cast<float4*>(&a.S[o]) = make_float4(0.f, 0.f, 0.f, 0.f);
       *reinterpret_cast<float4*>(&a.S[(size_t)a.n * a.R + o]) = make_float4(0.f, 0.f, 0.f, 0.f);
       s[0] += fabs(b0); s[1] += fabs(b1); s[2] += fabs(b2); s[3] += fabs(b3);
@@ -224,12 +227,10 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
           f[k] = 0.f;
           sel = true;
         }
-      if (sel) {
-        double2 h01 = *reinterpret_cast<const double2*>(&a.H[o]);
-        double2 h23 = *reinterpret_cast<const double2*>(&a.H[o + 2]);
-        h01.x += s[0]; h01.y += s[1]; h23.x += s[2]; h23.y += s[3];
-        *reinterpret_cast<double2*>(&a.H[o]) = h01;
-        *reinterpret_cast<double2*>(&a.H[o + 2]) = h23;
+      if (sel) {  // the stage's history increment: FP32 here, added into the FP64 H before the refresh
+        float4 g = *reinterpret_cast<const float4*>(&a.G[o]);
+        g.x += s[0]; g.y += s[1]; g.z += s[2]; g.w += s[3];
+        *reinterpret_cast<float4*>(&a.G[o]) = g;
       }
       // F is rewritten only where it changed
       const bool inflow = (acc.x != 0.f) | (acc.y != 0.f) | (acc.z != 0.f) | (acc.w != 0.f);
@@ -318,6 +319,23 @@ __global__ void __launch_bounds__(kMaxR) k_batch_step(BatchArgs a, double alpha,
   if (threadIdx.x == 0) {
     *sweeps += 1;
     if (s_all) __hip_atomic_store(a.all_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// end of a stage: H += G, G = 0 (before the exact residual reads H)
+__global__ void __launch_bounds__(256) k_batch_flush(BatchArgs a) {
+  const int64_t total = a.n * (int64_t)a.R / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += stride) {
+    const size_t o = (size_t)q * 4;
+    const float4 g = *reinterpret_cast<const float4*>(&a.G[o]);
+    if (g.x == 0.f && g.y == 0.f && g.z == 0.f && g.w == 0.f) continue;
+    double2 h01 = *reinterpret_cast<const double2*>(&a.H[o]);
+    double2 h23 = *reinterpret_cast<const double2*>(&a.H[o + 2]);
+    h01.x += g.x; h01.y += g.y; h23.x += g.z; h23.y += g.w;
+    *reinterpret_cast<double2*>(&a.H[o]) = h01;
+    *reinterpret_cast<double2*>(&a.H[o + 2]) = h23;
+    *reinterpret_cast<float4*>(&a.G[o]) = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 }
 
@@ -479,6 +497,7 @@ __global__ void k_batch_clear(BatchArgs a) {
 
 struct BatchWork {
   float* S = nullptr;
+  float* G = nullptr;
   uint8_t* act = nullptr;
   float* heavy_in = nullptr;
   double* racc = nullptr;
@@ -489,7 +508,7 @@ struct BatchWork {
 };
 
 static void free_work(BatchWork& w) {
-  for (void* p : {(void*)w.S, (void*)w.act, (void*)w.heavy_in, (void*)w.racc, (void*)w.part, (void*)w.lane,
+  for (void* p : {(void*)w.S, (void*)w.G, (void*)w.act, (void*)w.heavy_in, (void*)w.racc, (void*)w.part, (void*)w.lane,
                   (void*)w.flags, (void*)w.sweeps})
     (void)hipFree(p);
   w = BatchWork();
@@ -517,6 +536,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
       return fail(set_error(DITR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)));      \
   } while (0)
   B_TRY(hipMalloc((void**)&w.S, sizeof(float) * 2 * n * R));
+  B_TRY(hipMalloc((void**)&w.G, sizeof(float) * n * R));
   B_TRY(hipMalloc((void**)&w.act, 2 * n));
   B_TRY(hipMalloc((void**)&w.heavy_in, sizeof(float) * std::max(1, g->n_heavy) * R));
   B_TRY(hipMalloc((void**)&w.racc, sizeof(double) * std::max(1, g->n_heavy) * R));
@@ -546,6 +566,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
   a.F = d_f;
   a.H = d_h;
   a.S = w.S;
+  a.G = w.G;
   a.act = w.act;
   a.heavy_in = w.heavy_in;
   a.racc = w.racc;
@@ -606,6 +627,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
     // exact residual of every right-hand side; stage 2 aims below the target
     ++rounds;
     B_TRY(hipMemsetAsync(remaining, 0, sizeof(int), st));
+    k_batch_flush<<<4096, 256, 0, st>>>(a);
     k_batch_refresh<<<nblocks, kBB, 0, st>>>(a);
     if (a.n_chunks > 0) k_batch_refresh_heavy<<<a.n_chunks * kSub, kBB, 0, st>>>(a);
     k_batch_refresh_fin<<<kFinBlocks, kBB, 0, st>>>(a);
