@@ -17,6 +17,8 @@
 //
 // Graph preprocessing (partition ids, the local CSC with 16-bit local targets,
 // the external in-link lists) is built once per graph.
+#include <stdlib.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -1255,7 +1257,12 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, 
   }
   a.epoch0 = q.epoch + 1;
   const_cast<PartPlan&>(q).epoch += max_levels + 1;
-  int spin_limit = 1 << 24;  // polls of about a microsecond: a stuck wait ends within seconds
+  // polls of about a microsecond: a stuck wait ends within seconds. The
+  // environment variable DITR_SPIN_LIMIT lowers it (a test knob: 0 makes every
+  // wait that is not already satisfied time out at its first poll, so the
+  // error path runs with every wave leaving the kernel normally)
+  int spin_limit = 1 << 24;
+  if (const char* e = getenv("DITR_SPIN_LIMIT")) spin_limit = std::max(0, std::min(atoi(e), 1 << 24));
   void* args[] = {&a, &spin_limit};
   HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_part_resident<kPB>), dim3(a.K),
                                      dim3(kPB), args, (unsigned)lds, c->stream));

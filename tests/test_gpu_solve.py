@@ -384,6 +384,26 @@ def test_errors(ctx):
     g.close()
 
 
+def test_resident_wait_timeout_is_an_error(ctx, monkeypatch):
+    """The resident sweep's waits are bounded: with a spin limit of zero every
+    barrier or item wait that is not already satisfied times out at its first
+    poll, the workgroups leave the kernel, the solve returns DITR_EHIP, and the
+    next solve on the same context is unaffected."""
+    spec = ditgen.SMALL
+    cp, ri = ditgen.generate(spec)
+    b = ditgen.uniform_b(spec.n)
+    # 157 partitions of 64 nodes: the first workgroups at a barrier poll it
+    # long before the last one arrives
+    monkeypatch.setenv("DITR_SPIN_LIMIT", "0")
+    with pytest.raises(ditr.DitrError) as e:
+        gpu_solve(ctx, cp, ri, b, 1e-12, mode=ditr.MODE_PARTITION, part_nodes=64)
+    assert e.value.status == ditr.EHIP and "timed out" in str(e.value)
+    monkeypatch.delenv("DITR_SPIN_LIMIT")
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-12, mode=ditr.MODE_PARTITION, part_nodes=64)
+    check_parity(cp, ri, b, h, f, st, 1e-12, ref_tol=1e-14)
+    assert st.launches <= st.rounds  # resident again
+
+
 def test_abort_keeps_identity(ctx, headline):
     cp, ri, b, ref = headline
     g = ditr.Graph(ctx, *upload(cp, ri))
