@@ -485,26 +485,36 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
   const uint16_t* __restrict__ lidx =
       TARGETS_LDS ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1) : a.loc_idx + v.lbase;
   const long long Tq = 1LL << 32;  // T in fixed point
+  const float ddf = (float)a.dd;
   for (int s = s0; s < s1; ++s) {
     int passed = 0;
     for (int i = threadIdx.x; i < v.np; i += BLOCK) {
+      // everything the step needs is read at once (one LDS round trip)
       const long long f = v.Fq[i];
-      if (!(f > Tq || f < -Tq)) continue;
-      const long long sq = (long long)atomicExch(reinterpret_cast<unsigned long long*>(&v.Fq[i]), 0ull);
-      v.dH[i] += (float)((double)sq * quantum);
       const int od = v.odeg[i];
-      const long long w = od > 0 ? to_fixed((double)sq * (a.dd / (double)od)) : 0;
+      const int e0 = v.lptr[i], e1 = v.lptr[i + 1];
+      const float dh = v.dH[i];
+      // keeps the compiler from sinking these reads into the branch below,
+      // which would cost a second round trip for every node that passes
+      asm volatile("" ::"v"(od), "v"(e0), "v"(e1), "v"(dh));
+      if (!(f > Tq || f < -Tq)) continue;
+      // the fluid read leaves the node; what other threads push meanwhile
+      // stays there (an atomic subtract, no returned value to wait for)
+      add_fixed(&v.Fq[i], -f);
+      v.dH[i] = dh + (float)((double)f * quantum);
+      // share per target: FP32 reciprocal (the pushes need not be exact: the
+      // exact refresh recomputes F from H when the stage ends)
+      const long long w = od > 0 ? to_fixed((double)f * (double)(ddf * __builtin_amdgcn_rcpf((float)od))) : 0;
       edges += (double)od;
       diffs += 1.0;
       passed = 1;
-      const int e1 = v.lptr[i + 1];
-      for (int e = v.lptr[i]; e < e1; e += 8) {
+      for (int e = e0; e < e1; e += 8) {
         int t[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) t[q] = e + q < e1 ? (int)lidx[e + q] : -1;
+        for (int q = 0; q < 8; ++q) t[q] = lidx[min(e + q, e1 - 1)];  // in range, no per-slot branch
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-          if (t[q] >= 0) add_fixed(&v.Fq[t[q]], w);  // ds_add_u64
+          if (e + q < e1) add_fixed(&v.Fq[t[q]], w);  // ds_add_u64
       }
     }
     if (!__syncthreads_or(passed)) break;  // barrier + "did any node pass"
