@@ -58,7 +58,7 @@ int ditr_opts_default(ditr_opts* o) {
   if (!o) return set_error(DITR_EINVAL, "opts is NULL");
   memset(o, 0, sizeof(*o));
   o->alpha = 1.5;
-  o->refresh_at = 1e-5;
+  o->refresh_at = 0;  // the library's choice for the mode
   o->park_ratio = 0.5;
   o->rescale_cap = 4.0;
   o->mode = DITR_MODE_AUTO;
@@ -351,6 +351,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   ditr_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.alpha > 1)) return finish(set_error(DITR_EINVAL, "alpha must be > 1"));
+  if (!(o.refresh_at >= 0) || !std::isfinite(o.refresh_at))
+    return finish(set_error(DITR_EINVAL, "refresh_at must be finite and >= 0"));
   if (o.block == 0) o.block = 1024;
   if (o.max_rounds <= 0) o.max_rounds = 16;
   HIP_TRY(hipSetDevice(c->device));
@@ -459,6 +461,13 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     return DITR_OK;
   };
 
+  // first exact refresh (0: the library's choice). The FP32 history
+  // increments of the partitioned and pull sweeps round off about 2^-24 of the
+  // history a stage adds, a few 1e-7 ||B||_1 at d = 0.85: a stage run below that
+  // chases fluid the exact residual does not hold, one stopped far above it
+  // restarts the threshold early. The asynchronous kernel keeps F itself in
+  // FP32 and drifts more, so it refreshes earlier.
+  const double refresh_at = o.refresh_at > 0 ? o.refresh_at : (mode == DITR_MODE_ASYNC ? 1e-5 : 1e-7);
   int status = DITR_OK;
   double t_carry = 0;
   bool resident_ran = false;
@@ -473,7 +482,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     }
     // stage 1 stops at refresh_at ||B||_1, where the exact residual replaces the
     // FP32 fluid and its rounding drift; later stages aim below the target
-    const double stage = (!refreshed && r > o.refresh_at * b1) ? std::max(target, o.refresh_at * b1)
+    const double stage = (!refreshed && r > refresh_at * b1) ? std::max(target, refresh_at * b1)
                                                                : 0.5 * target;
     // the threshold continues from the previous round (never above max|F| / alpha);
     // the first one starts at max|F| / alpha or at the mean |F| if lower, so a
@@ -587,6 +596,8 @@ int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double*
   ditr_opts_default(&o);
   if (opts) o = *opts;
   if (!(o.alpha > 1)) return set_error(DITR_EINVAL, "alpha must be > 1");
+  if (!(o.refresh_at >= 0) || !std::isfinite(o.refresh_at))
+    return set_error(DITR_EINVAL, "refresh_at must be finite and >= 0");
   HIP_TRY(hipSetDevice(c->device));
   __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
   int rc = launch_reset_ctrl(c);

@@ -208,7 +208,7 @@ struct JParser {
 //         "part_nodes": .., "sweeps_per_claim": .., "seconds": .., "default_seconds": ..}
 struct Entry {
   uint64_t key = 0;
-  double alpha = 1.5, refresh_at = 1e-5;
+  double alpha = 1.5, refresh_at = 0;
   int part_type = DITR_PART_CB_INOUT, part_nodes = 0, m = 0;
   double seconds = 0, default_seconds = 0;
 };
@@ -245,13 +245,13 @@ bool read_cache(const char* path, std::vector<Entry>& out) {
       return v && v->kind == JVal::NUM ? v->num : dflt;
     };
     en.alpha = num("alpha", 1.5);
-    en.refresh_at = num("refresh_at", 1e-5);
+    en.refresh_at = num("refresh_at", 0);
     en.part_type = (int)num("part_type", DITR_PART_CB_INOUT);
     en.part_nodes = (int)num("part_nodes", 0);
     en.m = (int)num("sweeps_per_claim", 0);
     en.seconds = num("seconds", 0);
     en.default_seconds = num("default_seconds", 0);
-    if (!(en.alpha > 1) || !(en.refresh_at > 0) || en.part_nodes < 0 || en.m < 0 ||
+    if (!(en.alpha > 1) || !(en.refresh_at >= 0) || en.part_nodes < 0 || en.m < 0 ||
         (en.part_type != DITR_PART_CB && en.part_type != DITR_PART_UNIFORM &&
          en.part_type != DITR_PART_CB_INOUT))
       continue;
@@ -358,7 +358,7 @@ int ditr_tune_cache_get(const char* path, uint64_t key, ditr_opts* out) {
 int ditr_tune_cache_put(const char* path, uint64_t key, const ditr_opts* o, double seconds,
                         double default_seconds) {
   if (!path || !o) return set_error(DITR_EINVAL, "NULL argument");
-  if (!(o->alpha > 1) || !(o->refresh_at > 0) || o->part_nodes < 0 || o->sweeps_per_claim < 0 ||
+  if (!(o->alpha > 1) || !(o->refresh_at >= 0) || o->part_nodes < 0 || o->sweeps_per_claim < 0 ||
       (o->part_type != DITR_PART_CB && o->part_type != DITR_PART_UNIFORM &&
        o->part_type != DITR_PART_CB_INOUT))
     return set_error(DITR_EINVAL, "options out of range");
@@ -498,7 +498,7 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
       if ((rc = consider(e))) return rc;
     }
     // stage 4: first exact refresh
-    for (double ra : {1e-4, 1e-5, 1e-6}) {
+    for (double ra : {1e-5, 1e-6, 1e-7, 1e-8}) {
       Entry e = best;
       e.refresh_at = ra;
       if (ra == best.refresh_at) continue;
