@@ -78,7 +78,7 @@ typedef struct {
   double refresh_at;   /* first exact FP64 residual refresh once ||F||_1 <= refresh_at ||B||_1
                           (cancels FP32 rounding drift); >= 0; default 0, the library's
                           choice: 1e-7 (partitioned and pull sweeps), 1e-5 (asynchronous
-                          kernel, batched solve) */
+                          kernel), 1e-6 (batched solve) */
   double park_ratio;   /* a partition idles while its fluid is below park_ratio times its
                           node share of the remaining fluid (Section 2.4, r_k < T); default 0.5 */
   double rescale_cap;  /* max factor a reception may raise a partition threshold (Section 2.6) */

@@ -516,7 +516,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
           }
         }
         // no readback here: the refresh below ends with one, which also
-        // carries the barrier-timeout flag of this launch
+        // carries the wait-timeout flag of this launch
         if (!rc && resident) rc = t_end(1);
         if (rc) return finish(rc);
         if (resident) {
@@ -565,7 +565,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     if (!rc) rc = read_ctrl(c);
     if (rc) return finish(rc);
     if (resident_ran && c->ctrl_host->err == 2)
-      return finish(set_error(DITR_EHIP, "a grid barrier of the resident sweep timed out"));
+      return finish(set_error(DITR_EHIP, "a wait of the resident sweep timed out"));
     st.refreshes += 1;
     st.rounds += 1;
     refreshed = true;

@@ -586,7 +586,7 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
 
   k_batch_init<<<nblocks, kBB, 0, st>>>(a);
   k_batch_clear<<<2048, 256, 0, st>>>(a);
-  k_batch_setup<<<1, 256, 0, st>>>(a, o.alpha, std::max(rel_tol, o.refresh_at > 0 ? o.refresh_at : 1e-5), b1, resid);
+  k_batch_setup<<<1, 256, 0, st>>>(a, o.alpha, std::max(rel_tol, o.refresh_at > 0 ? o.refresh_at : 1e-6), b1, resid);
   B_TRY(hipGetLastError());
 
   // the sweep loop, captured once as a graph of kBatchSweeps (heavy, sweep, step)

@@ -65,11 +65,11 @@ struct PartPlan {
                                  //   slot q of a lane (-1: none)
   int32_t* unit_meta = nullptr;  // [n_units][64] per lane: (item + 1 for the lane that leads
                                  //   its group, else 0) << 3 | log2(lanes of the group)
-  unsigned long long* item_word = nullptr;  // [n_items] item inflow: FP32 bits | epoch << 32
+  unsigned long long* item_word = nullptr;  // [2][n_items] item inflow: FP32 bits | epoch << 32
   int32_t n_items = 0, n_units = 0;
   int64_t epoch = 0;             // epochs handed out to resident launches so far
   float* S = nullptr;            // [2][n] published p_i dH_i
-  int* counters = nullptr;       // [8] finished workgroups at [1], grid barrier at [2..4]
+  int* counters = nullptr;       // [8] finished workgroups at [1], level arrivals at [6..7]
   double* partials = nullptr;    // [2][K][4] per-workgroup sums
   int32_t n_heavy = 0;
   int32_t max_local_edges = 0;   // most local out-links in one partition

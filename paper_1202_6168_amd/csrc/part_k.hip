@@ -27,8 +27,8 @@
 namespace {
 
 constexpr int kPB = 1024;     // threads per partition workgroup
-constexpr int kStride = 4;    // doubles per block in the partials
-constexpr int kCounters = 8;  // launch finish count, grid barrier, stop vote
+constexpr int kStride = 8;    // doubles per block in the partials (sums, abort vote)
+constexpr int kCounters = 8;  // launch finish count, level arrivals of the resident sweep
 constexpr int kItem = 512;    // links of a heavy row summed by one wave (8 per lane)
 
 int grid_for(int64_t n, int block, int cap) {
@@ -170,14 +170,15 @@ struct PartArgs {
   const int32_t* __restrict__ item_row;     // item -> local row
   const int32_t* __restrict__ unit_src;     // [n_units][8][64] sources of the item work units
   const int32_t* __restrict__ unit_meta;    // [n_units][64] lane -> item it leads, group size
-  unsigned long long* item_word;            // [n_items] item inflow bits | epoch << 32
+  unsigned long long* item_word;            // [2][n_items] item inflow bits | epoch << 32 (resident: by level parity)
   int n_items, n_units;
   int epoch0;        // resident: epoch of level 0 (grows across launches)
   float* F;
   double* H;
   float* S;          // [2][n] published p_i dH_i
   double* partials;  // [2][K][kStride] per-workgroup sums (resident: by level parity)
-  int* counters;     // [1] finished workgroups (launches); [2], [3] grid barrier; [4] stop vote
+  int* counters;     // [1] finished workgroups (launches); [6], [7] resident: workgroups done with
+                     // the levels of each parity (monotonic within a launch)
   Ctrl* ctrl;
   const int* abort_flag;  // host abort word (mapped)
   int n_heavy;
@@ -330,7 +331,7 @@ __device__ __forceinline__ void unit_gather(const float* S_in, const UnitLane& L
 // the whole wave calls this (the butterfly shuffles over all 64 lanes)
 template <bool RESIDENT>
 __device__ __forceinline__ void unit_finish(const PartArgs& a, const UnitLane& L, const float (&v)[8],
-                                            int epoch) {
+                                            int epoch, int ib = 0) {
   double x = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) x += (double)v[q];
@@ -344,27 +345,27 @@ __device__ __forceinline__ void unit_finish(const PartArgs& a, const UnitLane& L
   if (item >= 0) {
     const unsigned long long w =
         ((unsigned long long)(unsigned)epoch << 32) | (unsigned long long)__float_as_uint((float)x);
-    if (RESIDENT) __hip_atomic_store(&a.item_word[item], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (RESIDENT) __hip_atomic_store(&a.item_word[ib + item], w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else a.item_word[item] = w;
   }
 }
 
 template <bool RESIDENT>
 __device__ __forceinline__ void unit_sum(const PartArgs& a, const float* S_in, const UnitLane& L,
-                                         int epoch) {
+                                         int epoch, int ib) {
   float v[8];
   unit_gather<RESIDENT>(S_in, L, v);
-  unit_finish<RESIDENT>(a, L, v, epoch);
+  unit_finish<RESIDENT>(a, L, v, epoch, ib);
 }
 
 // units first, first + stride, ... (the caller's wave)
 template <bool RESIDENT>
 __device__ void item_sums(const PartArgs& a, const float* S_in, int64_t first, int64_t stride,
-                          int epoch) {
+                          int epoch, int ib = 0) {
   for (int64_t u = first; u < a.n_units; u += stride) {
     UnitLane L;
     unit_load(a, u, L);
-    unit_sum<RESIDENT>(a, S_in, L, epoch);
+    unit_sum<RESIDENT>(a, S_in, L, epoch, ib);
   }
 }
 
@@ -413,7 +414,7 @@ __device__ __forceinline__ void light_apply(const PartView& v, const uint32_t (&
 // Returns false on a timed-out wait.
 template <int BLOCK, bool RESIDENT>
 __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const float* S_in, double inv_q,
-                            int epoch, int spin_limit, int skip = 0) {
+                            int epoch, int spin_limit, int skip = 0, int ib = 0) {
   const int tid = threadIdx.x;
   auto ld = [&](int32_t s) { return RESIDENT ? ld_agent(&S_in[s]) : S_in[s]; };
   const int e1 = a.ext_ptr[p + 1];
@@ -445,7 +446,7 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
       const int k = k0 + u * BLOCK;
       if (k < k1) {
         row[u] = a.item_row[k];
-        w[u] = RESIDENT ? __hip_atomic_load(&a.item_word[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+        w[u] = RESIDENT ? __hip_atomic_load(&a.item_word[ib + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                         : a.item_word[k];
       }
     }
@@ -462,7 +463,7 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
             __hip_atomic_store(&a.ctrl->err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }
-          w[u] = __hip_atomic_load(&a.item_word[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          w[u] = __hip_atomic_load(&a.item_word[ib + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!ok) continue;
       }
@@ -680,54 +681,50 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
 // ---------------------------------------------------- the resident sweep
 // Every value one workgroup of the resident sweep hands to another (published
 // shares, partial sums, heavy-row sums, the votes) is written and read with
-// agent-scope atomics, which bypass the per-XCD L2s, so a grid barrier needs
+// agent-scope atomics, which bypass the per-XCD L2s, so a level arrival needs
 // no cache maintenance: each thread waits until its own stores are
-// acknowledged, and thread 0 meets the others on two agent-scope words.
+// acknowledged, then thread 0 counts the workgroup in on an agent-scope word.
 __device__ __forceinline__ void wait_stores() {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // s_waitcnt vmcnt(0)
 }
 
-// Grid barrier of a cooperative launch (every workgroup resident): arrival
-// counter bar[0], generation bar[1]. Workgroups pass the barriers in the same
-// order and count them in `gen`. A wait longer than spin_limit polls sets
+// Wait of a cooperative launch (every workgroup resident) until a monotonic
+// arrival counter reaches `target`: thread 0 polls it at agent scope, the
+// workgroup meets on the result. A wait longer than spin_limit polls sets
 // ctrl->err = 2 and returns false; the caller then leaves the kernel, so every
 // wave exits even if some workgroup never arrives.
-__device__ bool grid_sync(int* bar, int K, int& gen, int spin_limit, int* err, int* s_ok) {
-  wait_stores();
-  __syncthreads();
-  const int target = gen + 1;
+__device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err, int* s_ok) {
   if (threadIdx.x == 0) {
-    int ok = 1;
-    const int t = __hip_atomic_fetch_add(&bar[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (t == K - 1) {
-      __hip_atomic_store(&bar[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      wait_stores();  // the reset lands before the release of the waiters
-      __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      int spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > spin_limit) {
-          ok = 0;
-          __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+    int ok = 1, spins = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > spin_limit) {
+        ok = 0;
+        __hip_atomic_store(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
     }
     *s_ok = ok;
   }
   __syncthreads();
-  gen = target;
   return *s_ok != 0;
 }
 
 // The partitioned sweep with every partition resident for a whole stage: the
 // partition is loaded into LDS once and stays there across threshold levels.
-// One level: outside inflow, up to m local sweeps at T, H += dH and the shares
-// p_i dH_i published; grid barrier; every workgroup reduces the same
-// per-workgroup sums in the same order, so all take the same stop decision and
-// the same next T (T / alpha). The shares alternate between two buffers, so
-// one barrier per level suffices. F goes back to memory when the stage ends.
+// Level l of a workgroup: wait until every workgroup has published level l-1
+// (an arrival count, not a barrier: the workgroups that finished first do not
+// wait for a release); gather the outside shares of level l-1 and run the
+// first local sweep while they land; finish the item sums, add the outside
+// fluid; read the per-workgroup sums of level l-1; further local sweeps;
+// publish H += dH and the shares p_i dH_i of level l and its own sums; arrive.
+// The stop, abort and next-threshold decisions come from the sums of level
+// l-1, which every workgroup reduces in the same order, so all take them at the
+// same level; the run therefore ends one level after the one whose sums met
+// the target. Shares, item words and sums alternate between two buffers by
+// level parity: a workgroup publishes level l only after every workgroup has
+// finished level l-1, so nobody still reads the level l-2 contents it
+// replaces. F goes back to memory when the stage ends.
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_limit) {
   const int tid = threadIdx.x;
@@ -737,11 +734,12 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   extern __shared__ __align__(16) unsigned char smem[];
   const int p = blockIdx.x;
   const PartView v = part_view(a, smem, p);
-  int* bar = a.counters + 2;
+  int* arrive = a.counters + 6;
   int* err = &a.ctrl->err;
   const double target = a.ctrl->target;
   double T = a.ctrl->T;
-  int gen = 0, parity = 0, done = 0, levels = 0;
+  int done = 0, levels = 0, stop = 0;
+  double edges_tail = 0, diffs_tail = 0;  // own counts of the last level, added at the end
 
   double quantum = fixed_quantum(T);
   part_load<BLOCK>(a, v, 1.0 / quantum);
@@ -756,9 +754,14 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   uint32_t lrow[kLight / 2];
   light_prep(a, p, lsrc, lrow);
   for (; levels < a.max_levels; ++levels) {
-    const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
-    float* S_out = a.S + (size_t)parity * a.n;
-    const int epoch = a.epoch0 + levels;
+    const int par = levels & 1;
+    const float* S_in = a.S + (size_t)(par ^ 1) * a.n;
+    float* S_out = a.S + (size_t)par * a.n;
+    const int epoch = a.epoch0 + levels, ib = par * a.n_items;
+    // everything of level l-1 is out (shares, sums); level 0 reads the zeroed
+    // buffer of parity 1
+    if (levels > 0 && !wait_count(&arrive[par ^ 1], a.K * ((levels - 1) / 2 + 1), spin_limit, err, &s_ok))
+      return;
     // the outside shares are gathered first and land during the first local
     // sweep; they join the fluid before the second one
     float iv[8], lv[kLight];
@@ -766,10 +769,38 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     light_gather(S_in, lsrc, lv);
     double edges = 0, diffs = 0;
     part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 0, 1);
-    if (unit0 < a.n_units) unit_finish<true>(a, L0, iv, epoch);
-    item_sums<true>(a, S_in, unit0 + n_waves, n_waves, epoch);
+    // the sums of level l-1, in flight while the outside fluid is added
+    const double* prev = a.partials + (size_t)(par ^ 1) * a.K * kStride;
+    double D = 0, M = 0, E = 0, P = 0;
+    if (levels > 0)
+      for (int k = tid; k < a.K; k += BLOCK) {
+        const double* q = prev + (size_t)kStride * k;
+        D += ld_agent(&q[0]);
+        M = fmax(M, ld_agent(&q[1]));
+        E += ld_agent(&q[2]);
+        P += ld_agent(&q[3]);
+      }
+    if (unit0 < a.n_units) unit_finish<true>(a, L0, iv, epoch, ib);
+    item_sums<true>(a, S_in, unit0 + n_waves, n_waves, epoch, ib);
     light_apply(v, lrow, lv, 1.0 / quantum);
-    if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, epoch, spin_limit, kLight)) return;
+    if (!part_inflow<BLOCK, true>(a, v, p, S_in, 1.0 / quantum, epoch, spin_limit, kLight, ib)) return;
+    // decisions from level l-1, the same in every workgroup
+    double Tn = T / (double)a.alpha;
+    if (levels > 0) {
+      block_reduce4<BLOCK>(D, M, E, P, red);
+      const bool aborted = ld_agent(&prev[4]) != 0.0;  // workgroup 0's vote
+      if (p == 0 && tid == 0) {
+        Ctrl* ctrl = a.ctrl;
+        ctrl->sum_abs = D;
+        __hip_atomic_fetch_add(&ctrl->edges, (unsigned long long)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&ctrl->diffusions, (unsigned long long)P, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (D <= target) done = stop = 1;
+      if (aborted) stop = 1;
+      if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
+      Tn = fmax(Tn, D * kPartTFloor);
+    }
     part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 1, a.m);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
@@ -777,60 +808,43 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     part_publish<BLOCK, true>(a, v, quantum, S_out, resid, fmx);
     if (unit0 < a.n_units) unit_load(a, unit0, L0);  // for the next level
     light_prep(a, p, lsrc, lrow);
-    // per-workgroup sums and the abort vote go to the slots of this level's
-    // parity: a workgroup can reach the next level's publish while another
-    // still reads this level's slots, never the one after
-    double* part = a.partials + (size_t)parity * a.K * kStride;
+    double* part = a.partials + (size_t)par * a.K * kStride;
     block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
+    edges_tail = edges;
+    diffs_tail = diffs;
     if (tid == 0) {
       double* q = part + (size_t)kStride * p;
       st_agent(&q[0], resid);
       st_agent(&q[1], fmx);
       st_agent(&q[2], edges);
       st_agent(&q[3], diffs);
-      if (p == 0) st_agent(&bar[2 + parity], ld_system(a.abort_flag) != 0 ? 1 : 0);
+      if (p == 0) st_agent(&q[4], ld_system(a.abort_flag) != 0 ? 1.0 : 0.0);
     }
-    if (!grid_sync(bar, a.K, gen, spin_limit, err, &s_ok)) return;
-
-    // the same global sums in every workgroup
-    double D = 0, M = 0, E = 0, P = 0;
-    for (int k = tid; k < a.K; k += BLOCK) {
-      const double* q = part + (size_t)kStride * k;
-      D += ld_agent(&q[0]);
-      M = fmax(M, ld_agent(&q[1]));
-      E += ld_agent(&q[2]);
-      P += ld_agent(&q[3]);
-    }
-    block_reduce4<BLOCK>(D, M, E, P, red);
-    if (p == 0 && tid == 0) {
-      Ctrl* ctrl = a.ctrl;
-      ctrl->sum_abs = D;
-      ctrl->edges += (unsigned long long)E;
-      ctrl->diffusions += (unsigned long long)P;
-      ctrl->sweeps += 1;
-    }
-    if (D <= target) {
-      done = 1;
+    // every wave's shares, H and sums are out before the arrival
+    wait_stores();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(&arrive[par], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (stop) {
       ++levels;
       break;
     }
-    if (ld_agent(&bar[2 + parity])) {
-      ++levels;
-      break;
-    }
-    double Tn = T / (double)a.alpha;
-    if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
-    Tn = fmax(Tn, D * kPartTFloor);
     // the fluid moves to the quantum of the next threshold
     const double qn = fixed_quantum(Tn), r = quantum / qn;
     for (int i = tid; i < v.np; i += BLOCK) v.Fq[i] = to_fixed((double)v.Fq[i] * r);
     __syncthreads();
     T = Tn;
     quantum = qn;
-    parity ^= 1;
   }
   for (int j = tid; j < v.np; j += BLOCK) a.F[v.lo + j] = (float)((double)v.Fq[a.inv[v.lo + j]] * quantum);
+  // the counts of the last level were not in any decision: each workgroup adds its own
+  if (tid == 0) {
+    __hip_atomic_fetch_add(&a.ctrl->edges, (unsigned long long)edges_tail, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&a.ctrl->diffusions, (unsigned long long)diffs_tail, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (p == 0 && tid == 0) {
+    a.ctrl->sweeps += (unsigned long long)levels;
     a.ctrl->T = T;
     a.ctrl->done = done;
   }
@@ -1019,8 +1033,8 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     if (!urc) urc = up(&q.unit_src, usrc);
     if (!urc) urc = up(&q.unit_meta, umeta);
     if (urc) { cleanup(); return urc; }
-    PP_TRY(hipMalloc((void**)&q.item_word, sizeof(unsigned long long) * std::max<size_t>(1, irow.size())));
-    PP_TRY(hipMemset(q.item_word, 0, sizeof(unsigned long long) * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMalloc((void**)&q.item_word, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
+    PP_TRY(hipMemset(q.item_word, 0, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
     // the unit table replaces the per-row source list
     PP_TRY(hipFree(q.heavy_src));
     q.heavy_src = nullptr;
@@ -1262,7 +1276,7 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, 
   // epochs of this launch's levels: above every flag an earlier launch stored
   const PartPlan& q = g->pp;
   if ((int64_t)q.epoch + max_levels + 1 >= (int64_t)1 << 30) {  // restart the epochs
-    HIP_TRY(hipMemsetAsync(q.item_word, 0, sizeof(unsigned long long) * std::max(1, q.n_items), c->stream));
+    HIP_TRY(hipMemsetAsync(q.item_word, 0, sizeof(unsigned long long) * 2 * std::max(1, q.n_items), c->stream));
     const_cast<PartPlan&>(q).epoch = 0;
   }
   a.epoch0 = q.epoch + 1;
