@@ -772,6 +772,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     // the sums of level l-1, in flight while the outside fluid is added
     const double* prev = a.partials + (size_t)(par ^ 1) * a.K * kStride;
     double D = 0, M = 0, E = 0, P = 0;
+    const bool aborted = levels > 0 && ld_agent(&prev[4]) != 0.0;  // workgroup 0's vote
     if (levels > 0)
       for (int k = tid; k < a.K; k += BLOCK) {
         const double* q = prev + (size_t)kStride * k;
@@ -788,7 +789,6 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     double Tn = T / (double)a.alpha;
     if (levels > 0) {
       block_reduce4<BLOCK>(D, M, E, P, red);
-      const bool aborted = ld_agent(&prev[4]) != 0.0;  // workgroup 0's vote
       if (p == 0 && tid == 0) {
         Ctrl* ctrl = a.ctrl;
         ctrl->sum_abs = D;
@@ -806,8 +806,6 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
     double resid = 0, fmx = 0;
     part_publish<BLOCK, true>(a, v, quantum, S_out, resid, fmx);
-    if (unit0 < a.n_units) unit_load(a, unit0, L0);  // for the next level
-    light_prep(a, p, lsrc, lrow);
     double* part = a.partials + (size_t)par * a.K * kStride;
     block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
     edges_tail = edges;
@@ -824,6 +822,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     wait_stores();
     __syncthreads();
     if (tid == 0) __hip_atomic_fetch_add(&arrive[par], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (unit0 < a.n_units) unit_load(a, unit0, L0);  // for the next level, after the arrival
+    light_prep(a, p, lsrc, lrow);
     if (stop) {
       ++levels;
       break;
