@@ -214,6 +214,25 @@ __device__ __forceinline__ void add_fixed(long long* p, long long v) {
 // quantum of the threshold T (a positive floor keeps 1/q finite when T = 0)
 __device__ __forceinline__ double fixed_quantum(double T) { return fmax(T, 1e-280) / kFix; }
 
+// Workgroup barrier for LDS traffic: each wave's LDS accesses complete before
+// it, while its global loads stay in flight. __syncthreads and its _or/_and
+// forms also wait for every outstanding global load, which would expose the
+// latency of the outside gathers at the first barrier after they are issued.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// block-wide OR of a predicate over one LDS slot per wave; callers alternate
+// two slot sets between consecutive calls, so one barrier per call suffices
+template <int NW>
+__device__ __forceinline__ int block_or(int pred, int* slots) {
+  const unsigned long long b = __ballot(pred);
+  if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = b != 0ull;
+  lds_barrier();
+  int any = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) any |= slots[w];
+  return any;
+}
+
 // A partition's view of the dynamic LDS, indexed by local id (the partition's
 // nodes renumbered in visiting order: node lo + j has local id inv[lo + j]):
 // fluid (fixed point), history increment of the level (FP32, added to the
@@ -471,7 +490,8 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
       if (x != 0.f) add_fixed(&v.Fq[row[u]], to_fixed((double)x * inv_q));
     }
   }
-  return __syncthreads_and(ok) != 0;
+  __shared__ int any_fail[BLOCK / 64];
+  return !block_or<BLOCK / 64>(!ok, any_fail);
 }
 
 // 3. local threshold sweeps s0..s1-1 at one T until none passes. Each
@@ -487,6 +507,7 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
       TARGETS_LDS ? reinterpret_cast<const uint16_t*>(v.lidx_words) + (v.lbase & 1) : a.loc_idx + v.lbase;
   const long long Tq = 1LL << 32;  // T in fixed point
   const float ddf = (float)a.dd;
+  __shared__ int any_passed[2][BLOCK / 64];
   for (int s = s0; s < s1; ++s) {
     int passed = 0;
     for (int i = threadIdx.x; i < v.np; i += BLOCK) {
@@ -518,7 +539,7 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
           if (e + q < e1) add_fixed(&v.Fq[t[q]], w);  // ds_add_u64
       }
     }
-    if (!__syncthreads_or(passed)) break;  // barrier + "did any node pass"
+    if (!block_or<BLOCK / 64>(passed, any_passed[s & 1])) break;  // barrier + "did any node pass"
   }
 }
 
@@ -584,14 +605,14 @@ __device__ void block_reduce4(double& r0, double& r1, double& r2, double& r3, do
   r1 = wave_maxd(r1);
   r2 = wave_sum(r2);
   r3 = wave_sum(r3);
-  __syncthreads();  // red may still be read by an earlier reduction
+  lds_barrier();  // red may still be read by an earlier reduction
   if (lane == 0) {
     red[0][wave] = r0;
     red[1][wave] = r1;
     red[2][wave] = r2;
     red[3][wave] = r3;
   }
-  __syncthreads();
+  lds_barrier();
   r0 = 0, r1 = 0, r2 = 0, r3 = 0;
   for (int w = 0; w < NW; ++w) {
     r0 += red[0][w];
@@ -706,7 +727,7 @@ __device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err,
     }
     *s_ok = ok;
   }
-  __syncthreads();
+  lds_barrier();
   return *s_ok != 0;
 }
 
@@ -831,7 +852,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     // the fluid moves to the quantum of the next threshold
     const double qn = fixed_quantum(Tn), r = quantum / qn;
     for (int i = tid; i < v.np; i += BLOCK) v.Fq[i] = to_fixed((double)v.Fq[i] * r);
-    __syncthreads();
+    lds_barrier();
     T = Tn;
     quantum = qn;
   }
