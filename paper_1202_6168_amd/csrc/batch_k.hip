@@ -190,24 +190,30 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
         *hp = make_float4(0.f, 0.f, 0.f, 0.f);  // accumulator of the next sweep
       }
     } else {
-      int32_t e = e0;
-      for (; e + 2 <= e1; e += 2) {  // two in-links in flight
-        const int32_t i0 = a.csr_col[e], i1 = a.csr_col[e + 1];
-        const uint8_t f0 = act_in[i0], f1 = act_in[i1];
-        if (on && f0) {
-          const float4 v = *reinterpret_cast<const float4*>(&S_in[(size_t)i0 * a.R + r0]);
-          acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+      // at most kHeavyRow (64) in-links: lane l reads in-link l and its source's
+      // activity flag, then the active sources' share rows are read four at a
+      // time (three dependent loads in all instead of three per pair of links)
+      const int32_t src = lane < e1 - e0 ? a.csr_col[e0 + lane] : -1;
+      unsigned long long m = __ballot(src >= 0 && act_in[src] != 0);
+      while (m) {
+        int32_t s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s[q] = -1;
+          if (m) {
+            const int b = __ffsll(m) - 1;
+            m &= m - 1;
+            s[q] = __builtin_amdgcn_readlane(src, b);
+          }
         }
-        if (on && f1) {
-          const float4 v = *reinterpret_cast<const float4*>(&S_in[(size_t)i1 * a.R + r0]);
-          acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
-        }
-      }
-      if (e < e1) {
-        const int32_t i0 = a.csr_col[e];
-        if (on && act_in[i0]) {
-          const float4 v = *reinterpret_cast<const float4*>(&S_in[(size_t)i0 * a.R + r0]);
-          acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        float4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          v[q] = on && s[q] >= 0 ? *reinterpret_cast<const float4*>(&S_in[(size_t)s[q] * a.R + r0])
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc.x += v[q].x; acc.y += v[q].y; acc.z += v[q].z; acc.w += v[q].w;
         }
       }
     }
