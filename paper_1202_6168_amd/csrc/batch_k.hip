@@ -139,11 +139,32 @@ __global__ void __launch_bounds__(kBB) k_batch_heavy(BatchArgs a, int parity) {
   const int se = min(a.chunk_end[c], sb + kHeavyChunk / kSub);
   const bool on = 4 * lane < a.R;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int e = sb + wave; e < se; e += kBB / 64) {
-    const int32_t i = a.csr_col[e];
-    if (!act_in[i] || !on) continue;
-    const float4 v = *reinterpret_cast<const float4*>(&S_in[(size_t)i * a.R + 4 * lane]);
-    acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+  // each wave takes 64 in-links at a time, one per lane (index and activity
+  // flag), then reads the active sources' share rows four at a time
+  for (int eb = sb + 64 * wave; eb < se; eb += kBB) {
+    const int32_t src = eb + lane < se ? a.csr_col[eb + lane] : -1;
+    unsigned long long m = __ballot(src >= 0 && act_in[src] != 0);
+    while (m) {
+      int32_t s4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        s4[q] = -1;
+        if (m) {
+          const int bit = __ffsll(m) - 1;
+          m &= m - 1;
+          s4[q] = __builtin_amdgcn_readlane(src, bit);
+        }
+      }
+      float4 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[q] = on && s4[q] >= 0 ? *reinterpret_cast<const float4*>(&S_in[(size_t)s4[q] * a.R + 4 * lane])
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc.x += v[q].x; acc.y += v[q].y; acc.z += v[q].z; acc.w += v[q].w;
+      }
+    }
   }
   __shared__ float4 red[kBB / 64][64];
   red[wave][lane] = acc;

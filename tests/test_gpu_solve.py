@@ -381,6 +381,11 @@ def test_errors(ctx):
     with pytest.raises(ditr.DitrError) as e:
         ditr.solve(ctx, g, b, h, f)
     assert e.value.status == ditr.ENONFINITE
+    b = torch.tensor([1.0, 2.0], dtype=torch.float64, device=dev)
+    for bad_refresh in (-1e-7, float("nan")):
+        with pytest.raises(ditr.DitrError) as e:
+            ditr.solve(ctx, g, b, h, f, opts=ditr.opts_default(refresh_at=bad_refresh))
+        assert e.value.status == ditr.EINVAL
     g.close()
 
 
