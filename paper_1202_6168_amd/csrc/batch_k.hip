@@ -202,6 +202,11 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
   const int64_t nw = (int64_t)gridDim.x * (kBB / 64);
   for (int64_t j = (int64_t)blockIdx.x * (kBB / 64) + wave; j < a.n; j += nw) {
     const int32_t e0 = a.row_ptr[j], e1 = a.row_ptr[j + 1];
+    // the row's own fluid and out-degree do not depend on the inflow: their
+    // loads go out first and land while the in-links are gathered
+    const size_t o = (size_t)j * a.R + r0;
+    const float4 f0 = on ? *reinterpret_cast<const float4*>(&a.F[o]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int deg = a.col_ptr[j + 1] - a.col_ptr[j];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (e1 - e0 > kHeavyRow) {
       if (on) {
@@ -241,10 +246,7 @@ __global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
     int any = 0;
     float4 so = make_float4(0.f, 0.f, 0.f, 0.f);
     if (on) {
-      const size_t o = (size_t)j * a.R + r0;
-      const float4 f0 = *reinterpret_cast<const float4*>(&a.F[o]);
       float f[4] = {f0.x + acc.x, f0.y + acc.y, f0.z + acc.z, f0.w + acc.w};
-      const int deg = a.col_ptr[j + 1] - a.col_ptr[j];
       const float p = deg > 0 ? a.d / (float)deg : 0.f;
       float s[4] = {0.f, 0.f, 0.f, 0.f};
       bool sel = false;
