@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(kBB) k_batch_heavy(BatchArgs a, int parity) {
 }
 
 // one batched threshold sweep: a wave per row
-__global__ void __launch_bounds__(kBB) k_batch_sweep(BatchArgs a, int parity) {
+__global__ void __launch_bounds__(kBB, 8) k_batch_sweep(BatchArgs a, int parity) {
   if (__hip_atomic_load(a.all_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const float* S_in = a.S + (size_t)(parity ^ 1) * a.n * a.R;
   float* S_out = a.S + (size_t)parity * a.n * a.R;
