@@ -47,7 +47,8 @@ typedef enum {
   DITR_EINVAL = -1,       /* bad argument (null pointer, size, damping outside (0,1), ...) */
   DITR_EGRAPH = -2,       /* CSC is malformed (col_ptr not monotone, row out of range, ...) */
   DITR_ENOMEM = -3,       /* device or pinned host allocation failed */
-  DITR_EHIP = -4,         /* a HIP runtime call failed */
+  DITR_EHIP = -4,         /* a HIP runtime call failed, or a bounded wait inside the resident
+                             partitioned sweep timed out (the kernel then exits normally) */
   DITR_ENONFINITE = -5    /* B or H_0 holds NaN or Inf */
 } ditr_status;
 
