@@ -11,7 +11,7 @@ import pytest
 
 import ditgen
 import oracle
-from conftest import D, sparse_p
+from conftest import D, csc_from_edges, sparse_p
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -78,6 +78,41 @@ def test_batched_uneven_and_uniform_columns(ctx):
     check_columns(cp, ri, B, H, F, per, 1e-9, [0, 1, 2, 3, 4, 6])
     # an all-zero right-hand side stays at H = 0 with nothing diffused
     assert np.all(H[:, 5] == 0) and np.all(F[:, 5] == 0) and per[5].edges == 0
+
+
+def _inlink_boundary_graph(n=3000, seed=11):
+    """Rows with exactly 63, 64 and 65 in-links (64 is the most a row sums one
+    link per lane; 65 goes to the heavy-row chunks), one with 200, rows with a
+    single in-link, a self-loop, a repeated link and dangling nodes; the rest
+    random with out-degree 1..8."""
+    rng = np.random.default_rng(seed)
+    edges = []
+    special = {10: 63, 11: 64, 12: 65, 13: 200, 14: 64}
+    for row, k in special.items():
+        srcs = rng.choice(np.arange(100, n), size=k, replace=False)
+        edges += [(int(s), row) for s in srcs]
+    edges += [(20, 21), (21, 20), (22, 22), (23, 24), (23, 24)]  # self-loop, repeated link
+    for s in range(100, n):
+        if rng.random() < 0.1:
+            continue  # many stay dangling (some also feed the special rows)
+        for t in rng.integers(100, n, size=rng.integers(1, 9)):  # rows below 100 keep their counts
+            edges.append((s, int(t)))
+    return csc_from_edges(n, edges)
+
+
+@pytest.mark.parametrize("R", [4, 256])
+def test_batched_inlink_boundaries(ctx, R):
+    """The in-link gathers of the batched sweep at their limits: rows of 63,
+    64 and 65 in-links with every lane on (R = 256) and with most lanes off
+    (R = 4); seed sets on the special rows and their sources."""
+    cp, ri = _inlink_boundary_graph()
+    n = cp.size - 1
+    sets = [np.array([10, 11, 12, 13, 14]), np.arange(100, 400), np.array([20, 22, 23])]
+    sets += list(ditgen.ppr_seed_sets(n, R - len(sets), seed=3))
+    B = ditgen.ppr_rhs_dense(n, sets)
+    H, F, tot, per = run_batched(ctx, cp, ri, B, 1e-9)
+    assert tot.status == ditr.OK
+    check_columns(cp, ri, B, H, F, per, 1e-9, sorted({0, 1, 2, R // 2, R - 1}))
 
 
 def test_batched_matches_plain_solves(ctx):
