@@ -435,18 +435,32 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   } ev_guard{ev};
   if (timed)
     for (int i = 0; i < 2 * kBatch; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+  // The interval ev[0]..ev[1] is read only once the stream has been
+  // synchronized for another reason (the readback after the refresh) or before
+  // the events are reused: waiting for it right after the launch would keep
+  // the host from queueing the refresh behind the kernel.
+  int64_t pending = 0;  // launches in the interval not yet added
+  auto t_flush = [&]() -> int {
+    if (!pending) return DITR_OK;
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    st.kernel_seconds += 1e-3 * ms;
+    st.timed_launches += pending;
+    pending = 0;
+    return DITR_OK;
+  };
   auto t_begin = [&]() -> int {
-    if (timed) HIP_TRY(hipEventRecord(ev[0], c->stream));
+    if (!timed) return DITR_OK;
+    const int rc2 = t_flush();
+    if (rc2) return rc2;
+    HIP_TRY(hipEventRecord(ev[0], c->stream));
     return DITR_OK;
   };
   auto t_end = [&](int64_t launches) -> int {
     if (!timed) return DITR_OK;
     HIP_TRY(hipEventRecord(ev[1], c->stream));
-    HIP_TRY(hipEventSynchronize(ev[1]));
-    float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
-    st.kernel_seconds += 1e-3 * ms;
-    st.timed_launches += launches;
+    pending = launches;
     return DITR_OK;
   };
   // sum the first `executed` launch intervals of a batch (later ones were no-ops)
@@ -563,6 +577,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     }
     rc = launch_refresh(c, g, d_b, d_h, d_f);
     if (!rc) rc = read_ctrl(c);
+    if (!rc) rc = t_flush();
     if (rc) return finish(rc);
     if (resident_ran && c->ctrl_host->err == 2)
       return finish(set_error(DITR_EHIP, "a wait of the resident sweep timed out"));
@@ -581,6 +596,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   st.sweeps = (int64_t)c->ctrl_host->sweeps;
   st.idle_polls = (int64_t)c->ctrl_host->idle_polls;
   st.resid_l1 = r;
+  rc = t_flush();
+  if (rc) return finish(rc);
   if (status == DITR_NOT_CONVERGED)
     set_error(status, "not converged after %d rounds (||F||_1 = %g, target %g)", st.rounds, r, target);
   return finish(status);
