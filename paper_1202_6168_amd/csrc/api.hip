@@ -505,11 +505,11 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     double T0 = st.rounds > 0 ? std::min(t_carry, fmax / o.alpha)
                               : std::min(fmax / o.alpha, r / (double)std::max<int64_t>(1, g->n));
     if (mode == DITR_MODE_PARTITION) T0 = std::max(T0, r * kPartTFloor);
-    rc = launch_set_launch_target(c, r, stage, T0);
+    // the partitioned sweep sets the launch target in its stage preparation
+    rc = mode == DITR_MODE_PARTITION ? launch_part_prepare(c, g, r, stage, T0)
+                                     : launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
     if (mode == DITR_MODE_PARTITION) {
-      rc = launch_part_prepare(c, g);
-      if (rc) return finish(rc);
       const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
       const int batch = kBatch;
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;

@@ -242,7 +242,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g);
 void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges);
-int launch_part_prepare(ditr_ctx* c, const ditr_graph* g);
+int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, double r0, double target, double T0);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
                        int nlaunch, hipEvent_t* ev);
 int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits);

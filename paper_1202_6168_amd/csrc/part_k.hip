@@ -1161,10 +1161,30 @@ __global__ void k_zero_i32p(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-int launch_part_prepare(ditr_ctx* c, const ditr_graph* g) {
+// Start of a stage of the partitioned sweep in one launch (each small launch
+// costs microseconds of dispatch): the stage's control words, zero counters,
+// zero shares.
+__global__ void k_part_prepare(Ctrl* ctrl, double r0, double target, double T0, int* counters, float* S,
+                               int64_t n2) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (i0 == 0) {
+    ctrl->destroyed = 0;
+    ctrl->r0 = r0;
+    ctrl->target = target;
+    ctrl->T = T0;
+    ctrl->done = 0;
+    ctrl->ticket = 0;
+    ctrl->passed = 0;
+  }
+  if (i0 < kCounters) counters[i0] = 0;
+  for (int64_t i = i0; i < n2; i += stride) S[i] = 0.f;
+}
+
+int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, double r0, double target, double T0) {
   const PartPlan& q = g->pp;
-  k_zero_i32p<<<1, 64, 0, c->stream>>>(q.counters, kCounters);
-  k_zero_f32p<<<std::min<int64_t>(4096, (2 * g->n + 255) / 256), 256, 0, c->stream>>>(q.S, 2 * g->n);
+  static_assert(kCounters <= 256, "the first block clears the counters");
+  k_part_prepare<<<std::min<int64_t>(4096, std::max<int64_t>(1, (2 * g->n + 255) / 256)), 256, 0, c->stream>>>(
+      c->ctrl, r0, target, T0, q.counters, q.S, 2 * g->n);
   HIP_TRY(hipGetLastError());
   return DITR_OK;
 }
