@@ -147,3 +147,44 @@ def test_batched_rejects_bad_shapes(ctx):
         ditr.solve_batched(ctx, g, b, torch.empty_like(b), torch.empty((2, 4), dtype=torch.float32, device=dev))
     assert e.value.status == ditr.ENONFINITE
     g.close()
+
+
+def test_batched_headline_size_256(ctx):
+    """The batched configuration at its own size: the 1e6-node headline graph
+    with the benchmark's 256 seed sets (log-uniform sizes 1..1000, seed 42) at
+    1e-8 per right-hand side. Its hub rows carry up to ~49K in-links, so their
+    inflow is summed in many 2048-link chunks with all 256 lanes on, which the
+    smaller batched cases never reach. Checked columns: the largest seed set,
+    a single seed, and the sets that hold a seed on a row with more than 2048
+    in-links (node 0, the largest hub, among them)."""
+    spec = ditgen.HEADLINE
+    cp, ri = ditgen.generate(spec)
+    n, R, tol = spec.n, 256, 1e-8
+    sets = ditgen.ppr_seed_sets(n, R, seed=42)
+    indeg = np.bincount(ri, minlength=n)
+    hubs = set(np.nonzero(indeg > 2048)[0].tolist())
+    sizes = [len(s) for s in sets]
+    largest = int(np.argmax(sizes))
+    single = sizes.index(1)
+    on_hub = [r for r, s in enumerate(sets) if hubs.intersection(s.tolist())]
+    assert on_hub and max(indeg[list(hubs)]) > 2048 * 8, "workload lost its multi-chunk hub rows"
+    cols = sorted({0, largest, single, *on_hub})
+    print("c4 columns", cols, "sizes", [sizes[r] for r in cols], flush=True)
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+    B = ditgen.ppr_rhs_dense(n, sets)
+    bt = torch.from_numpy(B).to(dev)
+    ht = torch.empty_like(bt)
+    ft = torch.empty((n, R), dtype=torch.float32, device=dev)
+    tot, per = ditr.solve_batched(ctx, g, bt, ht, ft, rel_tol=tol)
+    torch.cuda.synchronize()
+    assert tot.status == ditr.OK
+    assert all(p.status == ditr.OK and p.resid_l1 <= tol * p.b_l1 * (1 + 1e-12) for p in per)
+    idx = torch.tensor(cols, device=dev)
+    H = np.zeros((n, R))
+    F = np.zeros((n, R))
+    H[:, cols] = ht.index_select(1, idx).cpu().numpy()
+    F[:, cols] = ft.index_select(1, idx).cpu().numpy().astype(np.float64)
+    del bt, ht, ft
+    g.close()
+    check_columns(cp, ri, B, H, F, per, tol, cols)
