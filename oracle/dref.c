@@ -16,7 +16,13 @@
  *     ascending order, diffuse every node with |F_i| > T, then T <- T / alpha;
  *   - PageRank matrix of Section 2.2: p_ji = d / #out_i for each out-link
  *     i -> j; a node without out-link (dangling) only moves F_i into H_i;
- *   - partitions of Section 2.3: uniform and cost-balanced (CB).
+ *   - partitions of Section 2.3: uniform and cost-balanced (CB), and the
+ *     alternative the paper proposes there, blocks of equal internal p mass;
+ *   - the general matrix of Section 2: a weighted graph whose link j -> i
+ *     carries p_ij of either sign (one value per CSC entry), solved when P is
+ *     strictly contractive (Section 1, equation affine);
+ *   - the normalized node priority of Section 2.4, F_i / ((#in_i + 1)(#out_i + 1)),
+ *     used by the threshold test in place of F_i when asked for.
  *
  * Readings of points the paper leaves open (all listed in the design notes):
  *   - stop when ||F||_1 <= rel_tol * ||B||_1 (the paper's r/(1-d) test with
@@ -65,6 +71,29 @@ int dref_check_csc(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t
   return DREF_OK;
 }
 
+/* Column norm bound of a general matrix: max over columns of sum |p_ji|.
+ * The bound ||X - H||_1 <= ||F||_1 / (1 - c) of Section 2 holds with c = this
+ * norm when it is below 1 (||P||_1 <= c). */
+double dref_col_norm(int64_t n, const int32_t* col_ptr, const double* val) {
+  double c = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0;
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) s += fabs(val[e]);
+    if (s > c) c = s;
+  }
+  return c;
+}
+
+/* F = B + P H - H for a general matrix: entry e of column i carries val[e]. */
+int dref_fluid_from_history_w(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                              const double* val, const double* b, const double* h, double* f) {
+  (void)nnz;
+  for (int64_t i = 0; i < n; ++i) f[i] = b[i] - h[i];
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += val[e] * h[i];
+  return DREF_OK;
+}
+
 /* F = B + P H - H, straight from the definition of P (column i spreads
  * d / #out_i on each of its entries). */
 int dref_fluid_from_history(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
@@ -85,33 +114,52 @@ static double norm1(const double* x, int64_t n) {
   for (int64_t i = 0; i < n; ++i) s += fabs(x[i]);
   return s;
 }
-static double norminf(const double* x, int64_t n) {
+/* largest |F_i| / c_i (c = NULL: all c_i = 1) */
+static double max_scaled(const double* x, const double* c, int64_t n) {
   double m = 0;
-  for (int64_t i = 0; i < n; ++i)
-    if (fabs(x[i]) > m) m = fabs(x[i]);
+  for (int64_t i = 0; i < n; ++i) {
+    double v = c ? fabs(x[i]) / c[i] : fabs(x[i]);
+    if (v > m) m = v;
+  }
   return m;
 }
 
 /*
  * Sequential D-iteration until ||F||_1 <= rel_tol * ||B||_1.
+ *   val      NULL: the PageRank matrix (p_ji = d / #out_i, Section 2.2);
+ *            else the general matrix whose CSC entry e carries val[e]
+ *            (Section 2; d is then only the contraction factor of the bound)
+ *   priority 0: diffuse i when |F_i| > T (Section 2.4 cyclic test on F_i);
+ *            1: when |F_i| / ((#in_i + 1)(#out_i + 1)) > T, the normalized
+ *            priority of the argmax rule of Section 2.4 under the same cyclic
+ *            threshold (T_0 and the no-pass rule use the same ratio)
  *   h0       optional warm start (NULL = zero history)
  *   h, f     outputs [n]: history and remaining fluid
  *   r_hist   optional [r_hist_cap] record of ||F||_1 after each sweep
  * Returns DREF_OK, DREF_NOT_CONVERGED (max_sweeps hit; h, f still valid) or
  * a negative error.
  */
-int dref_solve(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx, double d,
-               const double* b, const double* h0, double rel_tol, double alpha, int64_t max_sweeps,
-               double* h, double* f, dref_stats* st, double* r_hist, int64_t r_hist_cap) {
+int dref_solve_ex(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx, double d,
+                  const double* val, int priority, const double* b, const double* h0, double rel_tol,
+                  double alpha, int64_t max_sweeps, double* h, double* f, dref_stats* st,
+                  double* r_hist, int64_t r_hist_cap) {
   memset(st, 0, sizeof(*st));
   if (!(d > 0 && d < 1) || !(alpha > 1) || !(rel_tol >= 0)) return DREF_EINVAL;
   int rc = dref_check_csc(n, nnz, col_ptr, row_idx);
   if (rc) return rc;
+  double* c = NULL; /* (#in_i + 1)(#out_i + 1), priority only */
+  if (priority) {
+    c = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!c) return DREF_ENOMEM;
+    for (int64_t e = 0; e < nnz; ++e) c[row_idx[e]] += 1.0; /* #in */
+    for (int64_t i = 0; i < n; ++i) c[i] = (c[i] + 1.0) * (double)(col_ptr[i + 1] - col_ptr[i] + 1);
+  }
 
   double t_start = now_s();
   if (h0) {
     memcpy(h, h0, sizeof(double) * n);
-    dref_fluid_from_history(n, nnz, col_ptr, row_idx, d, b, h, f);
+    if (val) dref_fluid_from_history_w(n, nnz, col_ptr, row_idx, val, b, h, f);
+    else dref_fluid_from_history(n, nnz, col_ptr, row_idx, d, b, h, f);
   } else {
     memset(h, 0, sizeof(double) * n);
     memcpy(f, b, sizeof(double) * n);
@@ -119,17 +167,20 @@ int dref_solve(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* ro
   st->b_l1 = norm1(b, n);
   const double target = rel_tol * st->b_l1;
   double r = norm1(f, n);
-  double T = norminf(f, n) / alpha;
+  double T = max_scaled(f, c, n) / alpha;
 
   while (r > target && st->sweeps < max_sweeps) {
     int64_t passed = 0;
     for (int64_t i = 0; i < n; ++i) {
-      if (!(fabs(f[i]) > T)) continue;
+      const double Ti = c ? T * c[i] : T;
+      if (!(fabs(f[i]) > Ti)) continue;
       double sent = f[i];
       h[i] += sent;
       f[i] = 0.0;
       int64_t k = col_ptr[i + 1] - col_ptr[i];
-      if (k > 0) {
+      if (val) {
+        for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += sent * val[e];
+      } else if (k > 0) {
         double p = d / (double)k; /* p_ji for every child j of i */
         for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += sent * p;
       }
@@ -144,14 +195,23 @@ int dref_solve(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* ro
     if (r_hist && st->sweeps <= r_hist_cap) r_hist[st->sweeps - 1] = r;
     T /= alpha;
     if (passed == 0) {
-      double m = norminf(f, n) / alpha;
+      double m = max_scaled(f, c, n) / alpha;
       if (m < T) T = m;
     }
   }
+  free(c);
   st->resid_l1 = r;
   st->converged = r <= target;
   st->seconds = now_s() - t_start;
   return st->converged ? DREF_OK : DREF_NOT_CONVERGED;
+}
+
+/* The PageRank matrix with the plain |F_i| test. */
+int dref_solve(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx, double d,
+               const double* b, const double* h0, double rel_tol, double alpha, int64_t max_sweeps,
+               double* h, double* f, dref_stats* st, double* r_hist, int64_t r_hist_cap) {
+  return dref_solve_ex(n, nnz, col_ptr, row_idx, d, NULL, 0, b, h0, rel_tol, alpha, max_sweeps, h, f,
+                       st, r_hist, r_hist_cap);
 }
 
 /* Uniform partition (Section 2.3): K contiguous ranges of floor(n/K) ids, the
@@ -202,5 +262,97 @@ int dref_partition_cb_inout(int64_t n, int64_t nnz, const int32_t* col_ptr, cons
   }
   ptr[K] = n;
   free(cost);
+  return DREF_OK;
+}
+
+/* Partition of equal internal p mass (the alternative balance proposed in
+ * Section 2.3): the mass of a block [a, b) is the sum of |p_ji| over the links
+ * i -> j with both ends in [a, b). Readings (the paper gives no rule):
+ *   - each link weighs floor(|p_ji| 2^32) integer units, so that block masses
+ *     are exact integers whatever order they are summed in;
+ *   - "equal" is taken as the contiguous K-block partition whose largest
+ *     block mass is smallest (t*), and among those the one whose blocks take,
+ *     from the left, as many nodes as they can: omega_{k+1} is the largest j
+ *     with m(omega_k, j) <= t*. When fewer than K blocks cover all nodes, the
+ *     remaining boundaries are n (empty blocks).
+ * val = NULL: PageRank weights d / #out_i. ptr has K+1 entries. */
+static int64_t link_units(const double* val, double d, const int32_t* col_ptr, int64_t i, int64_t e) {
+  double p = val ? fabs(val[e]) : d / (double)(col_ptr[i + 1] - col_ptr[i]);
+  return (int64_t)floor(p * 4294967296.0);
+}
+
+/* greedy blocks under the bound t; writes up to K+1 boundaries into ptr when
+ * ptr != NULL; returns the number of blocks needed to cover [0, n) */
+static int64_t pmass_greedy(int64_t n, const int32_t* col_ptr, const int32_t* row_idx,
+                            const int64_t* wout, const int32_t* in_ptr, const int32_t* in_src,
+                            const int64_t* win, int64_t t, int64_t K, int64_t* ptr) {
+  int64_t blocks = 1, a = 0, cur = 0;
+  if (ptr) ptr[0] = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    /* mass node j adds to the block [a, j): its links to [a, j] plus the links
+       from [a, j) into it */
+    int64_t inc = 0, self = 0;
+    for (int64_t e = col_ptr[j]; e < col_ptr[j + 1]; ++e) {
+      if (row_idx[e] >= a && row_idx[e] <= j) inc += wout[e];
+      if (row_idx[e] == j) self += wout[e];
+    }
+    for (int64_t q = in_ptr[j]; q < in_ptr[j + 1]; ++q)
+      if (in_src[q] >= a && in_src[q] < j) inc += win[q];
+    if (j > a && cur + inc > t) { /* close [a, j), start [j, ...) */
+      if (ptr && blocks < K) ptr[blocks] = j;
+      ++blocks;
+      a = j;
+      cur = self;
+    } else {
+      cur += inc;
+    }
+  }
+  if (ptr) {
+    for (int64_t k = blocks; k <= K; ++k) ptr[k] = n;
+  }
+  return blocks;
+}
+
+int dref_partition_pmass(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                         const double* val, double d, int64_t K, int64_t* ptr) {
+  if (K < 1 || K > (n > 0 ? n : 1)) return DREF_EINVAL;
+  int64_t* wout = (int64_t*)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(int64_t));
+  int32_t* in_ptr = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  int32_t* in_src = (int32_t*)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(int32_t));
+  int64_t* win = (int64_t*)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(int64_t));
+  int32_t* fill = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!wout || !in_ptr || !in_src || !win || !fill) {
+    free(wout), free(in_ptr), free(in_src), free(win), free(fill);
+    return DREF_ENOMEM;
+  }
+  /* link weights, and the in-links of every node (source and weight) */
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) wout[e] = link_units(val, d, col_ptr, i, e);
+  for (int64_t e = 0; e < nnz; ++e) in_ptr[row_idx[e] + 1] += 1;
+  for (int64_t j = 0; j < n; ++j) in_ptr[j + 1] += in_ptr[j];
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) {
+      int64_t q = in_ptr[row_idx[e]] + fill[row_idx[e]]++;
+      in_src[q] = (int32_t)i;
+      win[q] = wout[e];
+    }
+  /* t* by bisection on the integers: feasible(t) = greedy needs <= K blocks;
+     a single node's block holds its self-links, so t >= their largest mass */
+  int64_t lo = 0, hi = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t self = 0;
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e)
+      if (row_idx[e] == i) self += wout[e];
+    if (self > lo) lo = self;
+  }
+  for (int64_t e = 0; e < nnz; ++e) hi += wout[e];
+  if (hi < lo) hi = lo;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, mid, K, NULL) <= K) hi = mid;
+    else lo = mid + 1;
+  }
+  pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, lo, K, ptr);
+  free(wout), free(in_ptr), free(in_src), free(win), free(fill);
   return DREF_OK;
 }

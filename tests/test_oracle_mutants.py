@@ -18,6 +18,9 @@ import ditgen
 import oracle
 from conftest import D, csc_from_edges, dense_p, random_graph, sparse_p
 
+import sys
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
 SRC = os.path.join(os.path.dirname(os.path.abspath(oracle.__file__)), "dref.c")
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_small.json")
 
@@ -27,14 +30,29 @@ MUTANTS = {
     "damping_dropped": ("double p = d / (double)k; /* p_ji", "double p = 1.0 / (double)k; /* p_ji"),
     "history_overwritten": ("h[i] += sent;", "h[i] = sent;"),
     "zero_after_push": ("      f[i] = 0.0;\n      int64_t k", "      int64_t k"),
-    "signed_threshold": ("if (!(fabs(f[i]) > T)) continue;", "if (!(f[i] > T)) continue;"),
-    "identity_sign": ("f[i] = b[i] - h[i];", "f[i] = b[i] + h[i];"),
+    "signed_threshold": ("if (!(fabs(f[i]) > Ti)) continue;", "if (!(f[i] > Ti)) continue;"),
+    "identity_sign": ("f[i] = b[i] - h[i];\n  for (int64_t i = 0; i < n; ++i) {",
+                      "f[i] = b[i] + h[i];\n  for (int64_t i = 0; i < n; ++i) {"),
+    "weighted_identity_sign": ("f[i] = b[i] - h[i];\n  for (int64_t i = 0; i < n; ++i)\n",
+                               "f[i] = b[i] + h[i];\n  for (int64_t i = 0; i < n; ++i)\n"),
     "transposed_identity": ("for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[row_idx[e]] += p * h[i];",
                             "for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) f[i] += p * h[row_idx[e]];"),
     "cb_off_by_one": ("(int64_t)col_ptr[j] * K < k * L", "(int64_t)col_ptr[j] * K <= k * L"),
     "inout_drops_in_links": ("for (int64_t e = 0; e < nnz; ++e) cost[row_idx[e] + 1] += 1;",
                              "for (int64_t e = 0; e < 0; ++e) cost[row_idx[e] + 1] += 1;"),
     "inout_in_links_shifted": ("cost[row_idx[e] + 1] += 1;", "cost[row_idx[e]] += 1;"),
+    # general matrix, priority test, internal-mass partition
+    "weight_of_first_entry": ("f[row_idx[e]] += sent * val[e];", "f[row_idx[e]] += sent * val[col_ptr[i]];"),
+    "weighted_identity_transposed": ("f[row_idx[e]] += val[e] * h[i];", "f[i] += val[e] * h[row_idx[e]];"),
+    "priority_without_plus_one": ("c[i] = (c[i] + 1.0) * (double)(col_ptr[i + 1] - col_ptr[i] + 1);",
+                                  "c[i] = c[i] * (double)(col_ptr[i + 1] - col_ptr[i]);"),
+    "priority_in_links_only": ("c[i] = (c[i] + 1.0) * (double)(col_ptr[i + 1] - col_ptr[i] + 1);",
+                               "c[i] = (c[i] + 1.0);"),
+    "pmass_in_links_dropped": ("if (in_src[q] >= a && in_src[q] < j) inc += win[q];", ""),
+    "pmass_self_links_twice": ("if (in_src[q] >= a && in_src[q] < j) inc += win[q];",
+                               "if (in_src[q] >= a && in_src[q] <= j) inc += win[q];"),
+    "pmass_first_fit_not_min_max": ("if (pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, mid, K, NULL) <= K) hi = mid;",
+                                    "if (pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, mid, K, NULL) <= K + 1) hi = mid;"),
 }
 
 
@@ -119,11 +137,57 @@ def pin_suite(lib):
     return fails
 
 
+def general_pin_suite(lib):
+    """Pins of the general-matrix solve, the priority test and the internal-mass
+    partition (tests/test_oracle_general.py restated compactly)."""
+    import test_oracle_general as tg
+
+    fails = []
+    rng = np.random.default_rng(21)
+    n = 60
+    cp, ri = random_graph(n, rng, p_edge=0.08, self_loops=True, multi=True)
+    val = tg.signed_weights(cp, rng, 0.9)
+    b = rng.normal(size=n)
+    x = np.linalg.solve(np.eye(n) - tg.dense_w(cp, ri, val), b)
+    try:
+        r = oracle.solve(cp, ri, b, rel_tol=1e-14, val=val, d=0.9, max_sweeps=5000, lib=lib)
+        if not (r.converged and np.abs(r.h - x).sum() <= r.resid_l1 / (1 - 0.9) + 1e-12):
+            fails.append("general_dense")
+    except ValueError:
+        fails.append("general_dense")
+    h = rng.normal(size=n)
+    if np.abs(oracle.fluid_from_history_w(cp, ri, val, b, h, lib=lib)
+              - (b + tg.dense_w(cp, ri, val) @ h - h)).max() > 1e-13:
+        fails.append("general_identity")
+    fcp, fri = csc_from_edges(5, [(i, 0) for i in range(1, 5)])
+    r = oracle.solve(fcp, fri, np.array([1.0, .9, .9, .9, .9]), rel_tol=0.0, max_sweeps=1,
+                     priority=True, lib=lib)
+    if not np.array_equal(r.h, [0, .9, .9, .9, .9]):
+        fails.append("priority_fan_in")
+    ocp, ori = csc_from_edges(4, [(0, 1), (0, 2), (0, 3)])
+    r = oracle.solve(ocp, ori, np.array([1.0, .3, .3, .3]), rel_tol=0.0, max_sweeps=1,
+                     priority=True, lib=lib)
+    if not (r.h[0] == 1.0 and np.all(r.f == 0)):
+        fails.append("priority_fan_out")
+    for seed, K in [(0, 2), (1, 3), (3, 4)]:
+        g = np.random.default_rng(seed)
+        scp, sri = random_graph(9, g, p_edge=0.3, self_loops=True, multi=True)
+        w = tg.unit_weights(scp)
+        ptr = oracle.partition_pmass(scp, sri, K, lib=lib)
+        masses = [tg.block_mass(scp, sri, w, ptr[k], ptr[k + 1]) for k in range(K)]
+        if max(masses) != tg.brute_min_max(scp, sri, w, K):
+            fails.append("pmass_brute")
+            break
+    return fails
+
+
 def test_committed_oracle_passes(tmp_path):
-    assert pin_suite(build_variant(tmp_path, None)) == []
+    lib = build_variant(tmp_path, None)
+    assert pin_suite(lib) == [] and general_pin_suite(lib) == []
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(tmp_path, name):
-    fails = pin_suite(build_variant(tmp_path, name))
+    lib = build_variant(tmp_path, name)
+    fails = pin_suite(lib) + general_pin_suite(lib)
     assert fails, "planted mistake %r went unnoticed" % name
