@@ -173,6 +173,29 @@ int ditr_residual(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, const d
 int ditr_solve(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
                int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats);
 
+/* The plain solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, result and guarantees as ditr_solve, but its per-solve
+ * buffers (published shares, heavy-item words, per-workgroup sums, level
+ * counters, the exact residual's work arrays; about 16 n bytes) live in one
+ * static device array of the library, 64 MiB on every device it runs on, held
+ * until the process ends (ditr_noalloc_scratch_bytes() gives the size). The
+ * call performs no device or host allocation. The caller still passes B, H and
+ * F, and the context and graph are created beforehand as usual.
+ *   - DITR_MODE_AUTO / DITR_MODE_PARTITION only, without
+ *     DITR_FLAG_TIME_KERNELS; anything else returns DITR_EINVAL.
+ *   - A graph whose buffers exceed the static array returns DITR_EINVAL with
+ *     the sizes in the message (roughly n > 4e6).
+ *   - Every call on one device shares that device's array and finds the
+ *     previous call's contents there (the call clears what must start at
+ *     zero): calls that overlap on one device, from several threads or
+ *     contexts, race and must be serialized by the caller.
+ * Synchronizes. */
+int ditr_solve_noalloc(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, double* d_h,
+                       float* d_f, int warm, double rel_tol, const ditr_opts* opts,
+                       ditr_stats* stats);
+size_t ditr_noalloc_scratch_bytes(void);
+
 /* ---- batched personalized PageRank (step: many right-hand sides) -------- */
 /* Diffuse nrhs right-hand sides at once (multiple of 4, 4..256), each to its
  * own exact FP64 residual <= rel_tol * ||B_r||_1 (personalization vectors V of

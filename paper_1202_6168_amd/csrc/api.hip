@@ -108,6 +108,11 @@ int ditr_create(ditr_ctx** out, int device, void* hip_stream) {
     return set_error(DITR_ENOMEM, "device or pinned allocation failed");
   }
   *c->abort_host = 0;
+  const int nrc = noalloc_init(c);
+  if (nrc) {
+    ditr_destroy(c);
+    return nrc;
+  }
   if (hipMemset(c->ctrl, 0, sizeof(Ctrl)) != hipSuccess) {
     ditr_destroy(c);
     return set_error(DITR_EHIP, "hipMemset failed");
@@ -334,8 +339,15 @@ int ditr_residual(ditr_ctx* c, const ditr_graph* g, const double* d_b, const dou
   return DITR_OK;
 }
 
-int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
-               int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats) {
+}  // extern "C"
+
+// The plain solve (steps init, diffusion, transfer, residual, refresh) on the
+// per-solve buffers sb. noalloc: the caller may not allocate, so only the
+// partitioned sweep runs (its buffers are all in sb) and no timing events are
+// created.
+int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f, int warm,
+               double rel_tol, const ditr_opts* opts, ditr_stats* stats, const SolveBufs& sb,
+               bool noalloc) {
   const double t0 = now_s();
   ditr_stats st;
   memset(&st, 0, sizeof(st));
@@ -379,7 +391,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     if (rc) return finish(rc);
     if (c->ctrl_host->err) return finish(set_error(DITR_ENONFINITE, "B or H_0 holds NaN or Inf"));
     b1 = c->ctrl_host->sum_abs;
-    rc = launch_refresh(c, g, d_b, d_h, d_f);
+    rc = launch_refresh_bufs(c, g, d_b, d_h, d_f, sb.wh, sb.chunk_sum);
     if (!rc) rc = read_ctrl(c);
     if (rc) return finish(rc);
     r = c->ctrl_host->sum_abs;
@@ -398,6 +410,10 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   if (mode == DITR_MODE_AUTO) mode = DITR_MODE_PARTITION;
   if (mode != DITR_MODE_ASYNC && mode != DITR_MODE_SWEEP && mode != DITR_MODE_PARTITION)
     return finish(set_error(DITR_EINVAL, "unknown mode %d", mode));
+  if (noalloc && mode != DITR_MODE_PARTITION)
+    return finish(set_error(DITR_EINVAL, "the allocation-free solve runs the partitioned sweep only"));
+  if (noalloc && (o.flags & DITR_FLAG_TIME_KERNELS))
+    return finish(set_error(DITR_EINVAL, "the allocation-free solve creates no timing events"));
   if (mode == DITR_MODE_ASYNC) {
     cfg.block = o.block;
     cfg.lds_nodes = std::max<int>(1, g->max_part);
@@ -506,7 +522,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
                               : std::min(fmax / o.alpha, r / (double)std::max<int64_t>(1, g->n));
     if (mode == DITR_MODE_PARTITION) T0 = std::max(T0, r * kPartTFloor);
     // the partitioned sweep sets the launch target in its stage preparation
-    rc = mode == DITR_MODE_PARTITION ? launch_part_prepare(c, g, r, stage, T0)
+    rc = mode == DITR_MODE_PARTITION ? launch_part_prepare(c, g, sb, r, stage, T0)
                                      : launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
     if (mode == DITR_MODE_PARTITION) {
@@ -522,7 +538,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
         // every partition resident for the whole stage: one cooperative launch
         rc = t_begin();
         if (!rc) {
-          rc = launch_part_resident(c, g, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30));
+          rc = launch_part_resident(c, g, sb, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30));
           if (rc == DITR_EHIP) {  // cooperative launch refused: relaunch per level instead
             (void)hipGetLastError();
             resident = false;
@@ -542,7 +558,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       // rest of a batch into no-ops
       for (int64_t done_l = 0; !resident && done_l < budget; done_l += batch) {
         const uint64_t before = c->ctrl_host->sweeps;
-        rc = launch_part_sweeps(c, g, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr);
+        rc = launch_part_sweeps(c, g, sb, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr);
         if (!rc) rc = read_ctrl(c);
         if (!rc) rc = t_sum((int64_t)(c->ctrl_host->sweeps - before));
         if (rc) return finish(rc);
@@ -575,7 +591,7 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
         if (c->ctrl_host->done || __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST)) break;
       }
     }
-    rc = launch_refresh(c, g, d_b, d_h, d_f);
+    rc = launch_refresh_bufs(c, g, d_b, d_h, d_f, sb.wh, sb.chunk_sum);
     if (!rc) rc = read_ctrl(c);
     if (!rc) rc = t_flush();
     if (rc) return finish(rc);
@@ -601,6 +617,18 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   if (status == DITR_NOT_CONVERGED)
     set_error(status, "not converged after %d rounds (||F||_1 = %g, target %g)", st.rounds, r, target);
   return finish(status);
+}
+
+extern "C" {
+
+int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f,
+               int warm, double rel_tol, const ditr_opts* opts, ditr_stats* stats) {
+  if (!g) {
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (stats) stats->status = DITR_EINVAL;
+    return set_error(DITR_EINVAL, "NULL argument");
+  }
+  return solve_impl(c, g, d_b, d_h, d_f, warm, rel_tol, opts, stats, graph_bufs(g), false);
 }
 
 int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double* d_b, double* d_h,

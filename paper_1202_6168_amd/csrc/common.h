@@ -41,6 +41,8 @@ struct ditr_ctx {
   Ctrl* ctrl_host = nullptr;   // pinned mirror for readback
   double* partials = nullptr;  // reduction partials (2 doubles per block)
   size_t partials_cap = 0;     // in blocks
+  unsigned char* scratch = nullptr;  // this device's static scratch (ditr_solve_noalloc)
+  size_t scratch_bytes = 0;
 };
 
 // Tables of the partitioned sweep (part_k.hip), built per partition plan.
@@ -112,6 +114,19 @@ constexpr int kPartHeavy = 4;     // external in-links above which a row's inflo
 // lowest threshold of the partitioned sweep relative to the total fluid (its
 // LDS fluid is fixed point in units of T 2^-32)
 constexpr double kPartTFloor = 1.0 / 268435456.0;  // 2^-28
+
+// Per-solve device buffers of the plain solve. ditr_solve takes them from the
+// graph's tables; ditr_solve_noalloc carves them out of the static scratch.
+struct SolveBufs {
+  float* S = nullptr;                         // [2][n] published shares
+  unsigned long long* item_word = nullptr;    // [2][n_items] heavy-item inflow words
+  double* partials = nullptr;                 // [2][K][8] per-workgroup sums
+  int* counters = nullptr;                    // [8] finish count, level arrivals
+  double* wh = nullptr;                       // [n] p_ji H_i (exact residual)
+  double* chunk_sum = nullptr;                // [n_chunks] heavy-chunk sums (exact residual)
+  int64_t* epoch = nullptr;                   // host: item-word epochs handed out so far
+};
+SolveBufs graph_bufs(const ditr_graph* g);
 
 // ---- error reporting (api.hip) ------------------------------------------
 int set_error(int code, const char* fmt, ...);
@@ -230,6 +245,8 @@ int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);
 int launch_norm_f64(ditr_ctx* c, int64_t n, const double* x);
 int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f);
+int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f,
+                       double* wh, double* chunk_sum);
 int launch_reset_ctrl(ditr_ctx* c);
 int launch_set_launch_target(ditr_ctx* c, double r0, double target, double T0);
 int launch_fill_double(ditr_ctx* c, double* p, int64_t n, double v);
@@ -242,12 +259,17 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g);
 void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges);
-int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, double r0, double target, double T0);
-int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                       int nlaunch, hipEvent_t* ev);
+int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
+                        double target, double T0);
+int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
+                       double alpha, int m, int nlaunch, hipEvent_t* ev);
 int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits);
-int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                         int max_levels);
+int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
+                         double alpha, int m, int max_levels);
+int launch_zero_u64(ditr_ctx* c, unsigned long long* p, int64_t n);
+// static scratch of ditr_solve_noalloc (noalloc.hip): device address on the
+// context's device, looked up once per device at context creation
+int noalloc_init(ditr_ctx* c);
 struct PersistentCfg {
   int block;
   int grid;
@@ -270,3 +292,8 @@ int persistent_configure(ditr_ctx* c, size_t cu_lds, size_t block_lds);
 
 int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, double* d_h, float* d_f,
                 double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total);
+
+// host driver of the plain solve (api.hip)
+int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f, int warm,
+               double rel_tol, const ditr_opts* opts, ditr_stats* stats, const SolveBufs& sb,
+               bool noalloc);

@@ -1157,6 +1157,31 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   return DITR_OK;
 }
 
+__global__ void k_zero_u64p(unsigned long long* p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+int launch_zero_u64(ditr_ctx* c, unsigned long long* p, int64_t n) {
+  if (n <= 0) return DITR_OK;
+  k_zero_u64p<<<(unsigned)std::min<int64_t>(1024, (n + 255) / 256), 256, 0, c->stream>>>(p, n);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
+}
+
+SolveBufs graph_bufs(const ditr_graph* g) {
+  ditr_graph* m = const_cast<ditr_graph*>(g);
+  SolveBufs b;
+  b.S = m->pp.S;
+  b.item_word = m->pp.item_word;
+  b.partials = m->pp.partials;
+  b.counters = m->pp.counters;
+  b.wh = m->wh;
+  b.chunk_sum = m->chunk_sum;
+  b.epoch = &m->pp.epoch;
+  return b;
+}
+
 __global__ void k_zero_i32p(int* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -1180,11 +1205,11 @@ __global__ void k_part_prepare(Ctrl* ctrl, double r0, double target, double T0, 
   for (int64_t i = i0; i < n2; i += stride) S[i] = 0.f;
 }
 
-int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, double r0, double target, double T0) {
-  const PartPlan& q = g->pp;
+int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
+                        double target, double T0) {
   static_assert(kCounters <= 256, "the first block clears the counters");
   k_part_prepare<<<std::min<int64_t>(4096, std::max<int64_t>(1, (2 * g->n + 255) / 256)), 256, 0, c->stream>>>(
-      c->ctrl, r0, target, T0, q.counters, q.S, 2 * g->n);
+      c->ctrl, r0, target, T0, sb.counters, sb.S, 2 * g->n);
   HIP_TRY(hipGetLastError());
   return DITR_OK;
 }
@@ -1221,8 +1246,8 @@ int part_configure(ditr_ctx* c) {
 }
 
 namespace {
-int part_args(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m, PartArgs* out,
-              size_t* lds) {
+int part_args(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h, double alpha,
+              int m, PartArgs* out, size_t* lds) {
   const PartPlan& q = g->pp;
   PartArgs a;
   a.n = g->n;
@@ -1242,15 +1267,15 @@ int part_args(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alph
   a.item_row = q.item_row;
   a.unit_src = q.unit_src;
   a.unit_meta = q.unit_meta;
-  a.item_word = q.item_word;
+  a.item_word = sb.item_word;
   a.n_items = q.n_items;
   a.n_units = q.n_units;
   a.epoch0 = 0;
   a.F = f;
   a.H = h;
-  a.S = q.S;
-  a.partials = q.partials;
-  a.counters = q.counters;
+  a.S = sb.S;
+  a.partials = sb.partials;
+  a.counters = sb.counters;
   a.ctrl = c->ctrl;
   a.abort_flag = c->abort_dev;
   a.n_heavy = q.n_heavy;
@@ -1271,11 +1296,11 @@ int part_args(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alph
 }
 }  // namespace
 
-int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                       int nlaunch, hipEvent_t* ev) {
+int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
+                       double alpha, int m, int nlaunch, hipEvent_t* ev) {
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, f, h, alpha, m, &a, &lds);
+  int rc = part_args(c, g, sb, f, h, alpha, m, &a, &lds);
   if (rc) return rc;
   const PartPlan& q = g->pp;
   for (int s = 0; s < nlaunch; ++s) {
@@ -1296,7 +1321,7 @@ int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits) {
   *fits = false;
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, nullptr, nullptr, 1.5, 1, &a, &lds);
+  int rc = part_args(c, g, graph_bufs(g), nullptr, nullptr, 1.5, 1, &a, &lds);
   if (rc) return rc;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB>, kPB, lds) != hipSuccess) {
@@ -1307,21 +1332,22 @@ int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits) {
   return DITR_OK;
 }
 
-int launch_part_resident(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha, int m,
-                         int max_levels) {
+int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
+                         double alpha, int m, int max_levels) {
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, f, h, alpha, m, &a, &lds);
+  int rc = part_args(c, g, sb, f, h, alpha, m, &a, &lds);
   if (rc) return rc;
   a.max_levels = max_levels;
   // epochs of this launch's levels: above every flag an earlier launch stored
   const PartPlan& q = g->pp;
-  if ((int64_t)q.epoch + max_levels + 1 >= (int64_t)1 << 30) {  // restart the epochs
-    HIP_TRY(hipMemsetAsync(q.item_word, 0, sizeof(unsigned long long) * 2 * std::max(1, q.n_items), c->stream));
-    const_cast<PartPlan&>(q).epoch = 0;
+  if (*sb.epoch + max_levels + 1 >= (int64_t)1 << 30) {  // restart the epochs
+    rc = launch_zero_u64(c, sb.item_word, 2 * (int64_t)std::max(1, q.n_items));
+    if (rc) return rc;
+    *sb.epoch = 0;
   }
-  a.epoch0 = q.epoch + 1;
-  const_cast<PartPlan&>(q).epoch += max_levels + 1;
+  a.epoch0 = (int)(*sb.epoch + 1);
+  *sb.epoch += max_levels + 1;
   // polls of about a microsecond: a stuck wait ends within seconds. The
   // environment variable DITR_SPIN_LIMIT lowers it (a test knob: 0 makes every
   // wait that is not already satisfied time out at its first poll, so the

@@ -649,8 +649,14 @@ int launch_check_finite(ditr_ctx* c, int64_t n, const double* x) {
 }
 
 int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f) {
+  return launch_refresh_bufs(c, g, b, h, f, g->wh, g->chunk_sum);
+}
+
+// the same with the work arrays wh [n] and chunk_sum [n_chunks] given
+int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f,
+                        double* wh, double* chunk_sum) {
   const int64_t n = g->n;
-  k_refresh_wh<<<grid_for(n, 256, 8192), 256, 0, c->stream>>>(n, g->col_ptr, h, g->d, g->wh);
+  k_refresh_wh<<<grid_for(n, 256, 8192), 256, 0, c->stream>>>(n, g->col_ptr, h, g->d, wh);
   HIP_TRY(hipGetLastError());
   // light rows and the heavy chunks in one launch, then the heavy rows from
   // their chunk sums (every sum in a fixed order)
@@ -658,13 +664,13 @@ int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const doub
   const int nf = g->n_heavy > 0 ? std::min(64, (g->n_heavy + kRedBlock - 1) / kRedBlock) : 0;
   const int nl = grid_for(n, kRedBlock / 8, cap - nf);
   const int nc = g->n_heavy > 0 ? g->n_chunks : 0;
-  k_refresh_main<<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, g->wh, b, h, f,
+  k_refresh_main<<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, wh, b, h, f,
                                                        c->partials, g->chunk_beg, g->chunk_end,
-                                                       g->chunk_sum);
+                                                       chunk_sum);
   HIP_TRY(hipGetLastError());
   if (nf > 0) {
     k_refresh_heavy_fin<<<nf, kRedBlock, 0, c->stream>>>(g->n_heavy, g->heavy_rows, g->chunk_h,
-                                                         g->n_chunks, g->chunk_sum, b, h, f,
+                                                         g->n_chunks, chunk_sum, b, h, f,
                                                          c->partials + kPartialStride * nl);
     HIP_TRY(hipGetLastError());
   }

@@ -127,6 +127,9 @@ _SIGNATURES = {
     "ditr_residual": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)], _i32),
     "ditr_solve": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
                     ctypes.POINTER(Stats)], _i32),
+    "ditr_solve_noalloc": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
+                            ctypes.POINTER(Stats)], _i32),
+    "ditr_noalloc_scratch_bytes": ([], ctypes.c_size_t),
     "ditr_solve_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                             _vp, ctypes.POINTER(Stats)], _i32),
     "ditr_tune": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _dbl, _i32, ctypes.c_char_p,
@@ -306,6 +309,29 @@ def solve(ctx: Context, g: Graph, b, h, f, warm: bool = False, rel_tol: float = 
                           rel_tol, ctypes.byref(o), ctypes.byref(st))
     check(rc, allow)
     return st
+
+
+def solve_noalloc(ctx: Context, g: Graph, b, h, f, warm: bool = False, rel_tol: float = 1e-9,
+                  opts: Opts = None, allow=(OK, NOT_CONVERGED, ABORTED)) -> Stats:
+    """ditr_solve_noalloc: ditr_solve with its per-solve buffers in the library's
+    static device scratch (no allocation inside the call; partitioned sweep only)."""
+    torch = ctx.torch
+    if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
+        raise TypeError("b, h must be float64 and f float32")
+    for t in (b, h, f):
+        if t.numel() != g.n or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("b, h, f must be contiguous device vectors of length n")
+    st = Stats()
+    o = opts if opts is not None else opts_default()
+    rc = lib().ditr_solve_noalloc(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f), int(bool(warm)),
+                                  rel_tol, ctypes.byref(o), ctypes.byref(st))
+    check(rc, allow)
+    return st
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the static device scratch behind solve_noalloc."""
+    return int(lib().ditr_noalloc_scratch_bytes())
 
 
 def solve_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, opts: Opts = None,
