@@ -8,6 +8,7 @@ Functions keep the C names without the ``ditr_`` prefix.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import threading
@@ -202,10 +203,28 @@ def _stream(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+# Contexts still open when the interpreter exits are closed by an exit handler
+# registered after torch was imported, so it runs before torch and the HIP
+# runtime are torn down: every handle (graphs, networks, the context's stream
+# and pinned words) is released in a defined order, never from a finalizer
+# during interpreter shutdown.
+_live_contexts = weakref.WeakSet()
+_exit_hook = False
+
+
+def _close_all():
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """ditr_ctx on one device, issuing work on torch's current stream."""
 
     def __init__(self, device: int = 0, stream=None):
+        global _exit_hook
         import torch
 
         self.device = device
@@ -215,6 +234,11 @@ class Context:
         check(lib().ditr_create(ctypes.byref(h), device, s))
         self.handle = h
         self._children = weakref.WeakSet()  # graphs and networks, closed first
+        with _lock:
+            _live_contexts.add(self)
+            if not _exit_hook:
+                atexit.register(_close_all)
+                _exit_hook = True
 
     def abort(self):
         check(lib().ditr_abort(self.handle))
