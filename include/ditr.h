@@ -143,6 +143,22 @@ int ditr_abort(ditr_ctx* ctx);
 int ditr_graph_create(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64_t nnz,
                       const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
                       const ditr_opts* opts);
+/* General matrix (Section 2: p_ij is the weight of the link j -> i, of either
+ * sign; Section 1, equation affine, with any B): the same CSC plus d_val, one
+ * FP64 weight per CSC entry (device, borrowed, must outlive the graph). P must
+ * be strictly contractive in the l1 column norm, c = max_i sum_j |p_ji| < 1
+ * (the series sum_n P^n B then converges, and the bound of Section 2 holds with
+ * c in place of d); it is checked on the device, and DITR_EINVAL returned
+ * otherwise or for a NaN or Inf weight. ditr_solve then runs the pull sweep
+ * (DITR_MODE_AUTO or DITR_MODE_SWEEP); the other modes, the batched solve and
+ * the warm-start network take PageRank graphs only and return DITR_EINVAL.
+ * ditr_residual forms B + P H - H with these weights. Synchronizes. */
+int ditr_graph_create_weighted(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64_t nnz,
+                               const int32_t* d_col_ptr, const int32_t* d_row_idx,
+                               const double* d_val, const ditr_opts* opts);
+/* Contraction factor of g's matrix: the damping d of a PageRank graph, c of a
+ * general one (0 when it has no links). */
+int ditr_graph_contraction(const ditr_graph* g, double* c_out);
 int ditr_graph_destroy(ditr_graph* g);
 /* Number of partitions K of the plan and, if h_ptr != NULL and cap >= K+1,
  * the boundaries omega_0 = 0 < ... <= omega_K = n. Synchronizes. */

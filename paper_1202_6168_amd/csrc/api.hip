@@ -169,6 +169,8 @@ int ditr_graph_destroy(ditr_graph* g) {
   (void)hipDeviceSynchronize();
   (void)hipFree(g->row_ptr);
   (void)hipFree(g->csr_col);
+  (void)hipFree(g->csr_val);
+  (void)hipFree(g->colabs);
   (void)hipFree(g->heavy_rows);
   (void)hipFree(g->chunk_h);
   (void)hipFree(g->chunk_beg);
@@ -219,14 +221,18 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
   return DITR_OK;
 }
 
-int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
-                      const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
-                      const ditr_opts* opts) {
+}  // extern "C"
+
+// Graph upload for the PageRank matrix (d_val == nullptr, p_ji = damping / #out_i)
+// or a general matrix (one weight per CSC entry, Section 2).
+static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
+                             const int32_t* d_col_ptr, const int32_t* d_row_idx, const double* d_val,
+                             double damping, const ditr_opts* opts) {
   if (!c || !out) return set_error(DITR_EINVAL, "NULL argument");
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) - 1) return set_error(DITR_EINVAL, "n = %lld out of range", (long long)n);
   if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(DITR_EINVAL, "nnz = %lld out of range", (long long)nnz);
-  if (!(damping > 0 && damping < 1)) return set_error(DITR_EINVAL, "damping must lie in (0, 1)");
+  if (!d_val && !(damping > 0 && damping < 1)) return set_error(DITR_EINVAL, "damping must lie in (0, 1)");
   if (!d_col_ptr || (nnz > 0 && !d_row_idx)) return set_error(DITR_EINVAL, "NULL CSC array");
   ditr_opts o;
   ditr_opts_default(&o);
@@ -256,14 +262,38 @@ int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
   g->d = damping;
   g->col_ptr = d_col_ptr;
   g->row_idx = d_row_idx;
+  g->val = nnz > 0 ? d_val : nullptr;
   g->part_type = o.part_type;
   bool ok = hipMalloc((void**)&g->row_ptr, sizeof(int32_t) * (n + 1)) == hipSuccess &&
             hipMalloc((void**)&g->csr_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) == hipSuccess &&
             hipMalloc((void**)&g->heavy_rows, sizeof(int32_t) * n) == hipSuccess &&
             hipMalloc((void**)&g->wh, sizeof(double) * n) == hipSuccess;
+  if (ok && g->val)
+    ok = hipMalloc((void**)&g->csr_val, sizeof(double) * nnz) == hipSuccess &&
+         hipMalloc((void**)&g->colabs, sizeof(double) * n) == hipSuccess;
   if (!ok) {
     ditr_graph_destroy(g);
     return set_error(DITR_ENOMEM, "device allocation failed (graph of n = %lld)", (long long)n);
+  }
+  if (g->val) {
+    // a general matrix must be strictly contractive in the l1 column norm
+    // (Section 1: the series sum P^n B converges; the bound of Section 2 then
+    // holds with c = max_i sum_j |p_ji| in place of d)
+    double cmax = 0;
+    int bad = 0;
+    rc = launch_col_abs(c, g, &cmax, &bad);
+    if (rc) {
+      ditr_graph_destroy(g);
+      return rc;
+    }
+    if (bad || !(cmax < 1.0)) {
+      ditr_graph_destroy(g);
+      if (bad) return set_error(DITR_EINVAL, "a link weight is NaN or Inf");
+      return set_error(DITR_EINVAL, "P is not strictly contractive: largest column l1 norm %.17g >= 1", cmax);
+    }
+    g->d = cmax;
+  } else if (d_val) {
+    g->d = 0.0;  // no links: P = 0
   }
   rc = launch_build_transpose(c, g);
   if (!rc) rc = build_heavy_chunks(c, g);
@@ -312,6 +342,28 @@ int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
     return rc;
   }
   *out = g;
+  return DITR_OK;
+}
+
+extern "C" {
+
+int ditr_graph_create(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
+                      const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
+                      const ditr_opts* opts) {
+  return graph_create_impl(c, out, n, nnz, d_col_ptr, d_row_idx, nullptr, damping, opts);
+}
+
+int ditr_graph_create_weighted(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
+                               const int32_t* d_col_ptr, const int32_t* d_row_idx,
+                               const double* d_val, const ditr_opts* opts) {
+  if (nnz > 0 && !d_val) return set_error(DITR_EINVAL, "NULL weight array");
+  static const double kNoLinks = 0.0;
+  return graph_create_impl(c, out, n, nnz, d_col_ptr, d_row_idx, nnz > 0 ? d_val : &kNoLinks, 0.0, opts);
+}
+
+int ditr_graph_contraction(const ditr_graph* g, double* c_out) {
+  if (!g || !c_out) return set_error(DITR_EINVAL, "NULL argument");
+  *c_out = g->d;
   return DITR_OK;
 }
 
@@ -407,7 +459,10 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   PersistentCfg cfg;
   memset(&cfg, 0, sizeof(cfg));
   int mode = o.mode;
-  if (mode == DITR_MODE_AUTO) mode = DITR_MODE_PARTITION;
+  const bool general = g->val != nullptr || g->colabs != nullptr;
+  if (mode == DITR_MODE_AUTO) mode = general ? DITR_MODE_SWEEP : DITR_MODE_PARTITION;
+  if (general && mode != DITR_MODE_SWEEP)
+    return finish(set_error(DITR_EINVAL, "a general matrix is solved by the pull sweep (DITR_MODE_SWEEP)"));
   if (mode != DITR_MODE_ASYNC && mode != DITR_MODE_SWEEP && mode != DITR_MODE_PARTITION)
     return finish(set_error(DITR_EINVAL, "unknown mode %d", mode));
   if (noalloc && mode != DITR_MODE_PARTITION)
@@ -643,6 +698,7 @@ int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double*
   if (!(o.alpha > 1)) return set_error(DITR_EINVAL, "alpha must be > 1");
   if (!(o.refresh_at >= 0) || !std::isfinite(o.refresh_at))
     return set_error(DITR_EINVAL, "refresh_at must be finite and >= 0");
+  if (g->csr_val) return set_error(DITR_EINVAL, "the batched solve takes PageRank graphs (no link weights)");
   HIP_TRY(hipSetDevice(c->device));
   __atomic_store_n(c->abort_host, 0, __ATOMIC_SEQ_CST);
   int rc = launch_reset_ctrl(c);

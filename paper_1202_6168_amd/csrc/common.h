@@ -85,8 +85,12 @@ struct ditr_graph {
   double d = 0.85;
   const int32_t* col_ptr = nullptr;  // borrowed
   const int32_t* row_idx = nullptr;  // borrowed
+  const double* val = nullptr;       // borrowed: weight of each CSC entry (general matrix), or
+                                     //   nullptr for the PageRank weights d / #out_i
   int32_t* row_ptr = nullptr;        // transpose (CSR): in-links of each node
   int32_t* csr_col = nullptr;
+  double* csr_val = nullptr;         // general matrix: the weights in CSR order
+  double* colabs = nullptr;          // general matrix: sum |p_ji| of each column
   int32_t* heavy_rows = nullptr;     // rows with in-degree > kHeavyRow, ascending
   int32_t n_heavy = 0;
   int32_t* chunk_h = nullptr;        // heavy chunk -> index into heavy_rows
@@ -237,6 +241,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 int launch_validate_csc(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr,
                         const int32_t* row_idx);
 int launch_build_transpose(ditr_ctx* c, ditr_graph* g);
+int launch_col_abs(ditr_ctx* c, ditr_graph* g, double* h_max, int* h_bad);
 int launch_partition(ditr_ctx* c, int64_t n, const int32_t* col_ptr, const int32_t* row_ptr,
                      int part_type, int64_t K, int64_t* out64, int32_t* out32);
 int launch_in_prefix(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* row_idx, int32_t* out);

@@ -882,6 +882,7 @@ int ditr_gnn_set_params(ditr_gnn* m, const float* h_theta) {
 }
 
 int ditr_gnn_forward(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, float* d_yhat) {
+  if (g && g->csr_val) return set_error(DITR_EINVAL, "the warm-start network takes PageRank graphs");
   int rc = check_net(c, m, g);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(c->device));
@@ -913,6 +914,7 @@ int ditr_gnn_activation(ditr_ctx* c, const ditr_gnn* m, int which, int64_t n, ui
 
 int ditr_gnn_targets(ditr_ctx* c, const ditr_graph* g, const double* d_h, double b_l1, float* d_y,
                      float* d_w) {
+  if (g && g->csr_val) return set_error(DITR_EINVAL, "the warm-start network takes PageRank graphs");
   if (!c || !g || !d_h || !d_y || !d_w) return set_error(DITR_EINVAL, "NULL argument");
   if (!(b_l1 > 0) || !std::isfinite(b_l1)) return set_error(DITR_EINVAL, "b_l1 must be > 0");
   HIP_TRY(hipSetDevice(c->device));
@@ -937,6 +939,7 @@ int ditr_gnn_targets(ditr_ctx* c, const ditr_graph* g, const double* d_h, double
 
 int ditr_gnn_grad(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* d_y, const float* d_w,
                   float* d_grad, double* h_loss) {
+  if (g && g->csr_val) return set_error(DITR_EINVAL, "the warm-start network takes PageRank graphs");
   int rc = check_net(c, m, g);
   if (rc) return rc;
   if (!d_y || !d_w) return set_error(DITR_EINVAL, "NULL argument");
@@ -955,6 +958,7 @@ int ditr_gnn_grad(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* d_
 
 int ditr_gnn_train_step(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const float* d_y,
                         const float* d_w, double lr, double* h_loss) {
+  if (g && g->csr_val) return set_error(DITR_EINVAL, "the warm-start network takes PageRank graphs");
   if (!(lr > 0) || !std::isfinite(lr)) return set_error(DITR_EINVAL, "lr must be > 0");
   int rc = ditr_gnn_grad(c, m, g, d_y, d_w, nullptr, nullptr);
   if (rc) return rc;
@@ -976,6 +980,7 @@ int ditr_gnn_train_step(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const flo
 
 int ditr_gnn_predict_h0(ditr_ctx* c, ditr_gnn* m, const ditr_graph* g, const double* d_b,
                         double* d_h0, float* d_f0, ditr_gnn_start* info) {
+  if (g && g->csr_val) return set_error(DITR_EINVAL, "the warm-start network takes PageRank graphs");
   const double t0 = wall_now();
   int rc = check_net(c, m, g);
   if (rc) return rc;

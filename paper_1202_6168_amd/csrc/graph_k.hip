@@ -1,6 +1,8 @@
 // Graph preparation kernels: CSC validation, the CSR transpose used by the
 // exact residual, and the partition plan of Section 2.3 (uniform and
 // cost-balanced node ranges).
+#include <string.h>
+
 #include "common.h"
 
 namespace {
@@ -117,14 +119,38 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t* in, in
 }
 
 // cursor[j] starts at row_ptr[j]; every CSC entry (j in column i) lands in row j
+// (with its weight, for a general matrix)
 __global__ void k_fill_csr(int64_t n, const int32_t* __restrict__ col_ptr,
-                           const int32_t* __restrict__ row_idx, int32_t* cursor, int32_t* csr_col) {
+                           const int32_t* __restrict__ row_idx, const double* __restrict__ val,
+                           int32_t* cursor, int32_t* csr_col, double* csr_val) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride)
     for (int32_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) {
       int32_t pos = atomicAdd(&cursor[row_idx[e]], 1);
       csr_col[pos] = (int32_t)i;
+      if (val) csr_val[pos] = val[e];
     }
+}
+
+// General matrix: colabs[i] = sum |p_ji| over column i, the largest of them
+// (the contraction factor of the bound ||X - H||_1 <= ||F||_1 / (1 - c),
+// Section 2) as the bits of a non-negative double, err = 1 for a NaN or Inf.
+__global__ void k_col_abs(int64_t n, const int32_t* __restrict__ col_ptr, const double* __restrict__ val,
+                          double* colabs, unsigned long long* max_bits, int* err) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long m = 0;
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    double s = 0;
+    for (int32_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) {
+      bad |= !isfinite(val[e]);
+      s += fabs(val[e]);
+    }
+    colabs[i] = s;
+    if (isfinite(s)) m = max(m, (unsigned long long)__double_as_longlong(s));
+  }
+  if (bad) atomicOr(err, 1);
+  if (m) atomicMax(max_bits, m);
 }
 
 __global__ void k_heavy_rows(int64_t n, const int32_t* __restrict__ row_ptr, int32_t* list,
@@ -210,8 +236,8 @@ int launch_build_transpose(ditr_ctx* c, ditr_graph* g) {
   HIP_TRY(hipMemcpyAsync(cnt, g->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice,
                          c->stream));
   if (n > 0)
-    k_fill_csr<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(n, g->col_ptr, g->row_idx, cnt,
-                                                              g->csr_col);
+    k_fill_csr<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(n, g->col_ptr, g->row_idx, g->val, cnt,
+                                                              g->csr_col, g->csr_val);
   int* hcount = &c->ctrl->err;
   HIP_TRY(hipMemsetAsync(hcount, 0, sizeof(int), c->stream));
   if (n > 0)
@@ -245,4 +271,25 @@ int launch_in_prefix(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* row_idx
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(cnt);
   return rc;
+}
+
+// column l1 norms of a general matrix into g->colabs; the largest into *h_max
+// and 1 into *h_bad if a weight is NaN or Inf. Synchronizes.
+int launch_col_abs(ditr_ctx* c, ditr_graph* g, double* h_max, int* h_bad) {
+  int* err = &c->ctrl->err;
+  unsigned long long* mx = reinterpret_cast<unsigned long long*>(&c->ctrl->max_abs);
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), c->stream));
+  HIP_TRY(hipMemsetAsync(mx, 0, sizeof(unsigned long long), c->stream));
+  k_col_abs<<<grid_for(g->n, kBlock), kBlock, 0, c->stream>>>(g->n, g->col_ptr, g->val, g->colabs, mx, err);
+  HIP_TRY(hipGetLastError());
+  unsigned long long bits = 0;
+  int bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, mx, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double m;
+  memcpy(&m, &bits, sizeof(m));
+  *h_max = m;
+  *h_bad = bad;
+  return DITR_OK;
 }

@@ -30,9 +30,11 @@ struct PullArgs {
   const int32_t* __restrict__ chunk_h;
   const int32_t* __restrict__ chunk_beg;
   const int32_t* __restrict__ chunk_end;
+  const double* __restrict__ csr_val;  // general matrix: weight of each CSR entry (else nullptr)
+  const double* __restrict__ colabs;   // general matrix: sum |p_ji| of each column
   float* F;
   double* H;
-  float* S;          // [2][n]
+  float* S;          // [2][n] PageRank: sent * d / #out_i; general matrix: sent
   double* heavy_in;  // [2][n_heavy]
   double* partials;
   Ctrl* ctrl;
@@ -50,6 +52,9 @@ __device__ __forceinline__ int find_heavy(const int32_t* rows, int nh, int j) {
   return lo;
 }
 
+// W: general matrix (an in-link's share is its weight times the source's sent
+// fluid) instead of the PageRank shares published per source
+template <bool W>
 __global__ void __launch_bounds__(kPullBlock) k_pull_sweep(PullArgs a, int parity) {
   if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;  // written by the previous sweep
@@ -62,7 +67,8 @@ __global__ void __launch_bounds__(kPullBlock) k_pull_sweep(PullArgs a, int parit
     // ---- one chunk of the in-links of a heavy row
     const int c = blockIdx.x - a.n_light_blocks;
     double acc = 0;
-    for (int e = a.chunk_beg[c] + tid; e < a.chunk_end[c]; e += kPullBlock) acc += S_in[a.csr_col[e]];
+    for (int e = a.chunk_beg[c] + tid; e < a.chunk_end[c]; e += kPullBlock)
+      acc += W ? a.csr_val[e] * (double)S_in[a.csr_col[e]] : (double)S_in[a.csr_col[e]];
     acc = wave_sum(acc);
     __shared__ double red[kPullBlock / 64];
     if ((tid & 63) == 0) red[tid >> 6] = acc;
@@ -95,20 +101,29 @@ __global__ void __launch_bounds__(kPullBlock) k_pull_sweep(PullArgs a, int parit
       hin_prev[h] = 0.0;  // becomes the accumulator of the next sweep
     } else {
       int32_t e = r0;
-      for (; e + 4 <= r1; e += 4) {  // four index loads, then four gathers
-        const int32_t c0 = a.csr_col[e], c1 = a.csr_col[e + 1], c2 = a.csr_col[e + 2],
-                      c3 = a.csr_col[e + 3];
-        acc += (double)S_in[c0] + (double)S_in[c1] + (double)S_in[c2] + (double)S_in[c3];
+      if (W) {
+        for (; e < r1; ++e) acc += a.csr_val[e] * (double)S_in[a.csr_col[e]];
+      } else {
+        for (; e + 4 <= r1; e += 4) {  // four index loads, then four gathers
+          const int32_t c0 = a.csr_col[e], c1 = a.csr_col[e + 1], c2 = a.csr_col[e + 2],
+                        c3 = a.csr_col[e + 3];
+          acc += (double)S_in[c0] + (double)S_in[c1] + (double)S_in[c2] + (double)S_in[c3];
+        }
+        for (; e < r1; ++e) acc += S_in[a.csr_col[e]];
       }
-      for (; e < r1; ++e) acc += S_in[a.csr_col[e]];
     }
     float f = (float)((double)fj + acc);
     float s_out = 0.f;
     if (fabsf(f) > T) {
       const int deg = a.col_ptr[j + 1] - a.col_ptr[j];
       a.H[j] += (double)f;
-      s_out = deg > 0 ? f * (d / (float)deg) : 0.f;
-      if (deg > 0) resid += (double)d * fabs((double)f);
+      if (W) {
+        s_out = deg > 0 ? f : 0.f;
+        resid += a.colabs[j] * fabs((double)f);  // l1 mass of the shares in flight
+      } else {
+        s_out = deg > 0 ? f * (d / (float)deg) : 0.f;
+        if (deg > 0) resid += (double)d * fabs((double)f);
+      }
       edges += deg;
       diffs += 1;
       f = 0.f;
@@ -279,6 +294,8 @@ int launch_pull_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   a.chunk_h = g->chunk_h;
   a.chunk_beg = g->chunk_beg;
   a.chunk_end = g->chunk_end;
+  a.csr_val = g->csr_val;
+  a.colabs = g->colabs;
   a.F = f;
   a.H = h;
   a.S = g->pull_s;
@@ -290,7 +307,8 @@ int launch_pull_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, do
   a.d = (float)g->d;
   const int grid = a.n_light_blocks + g->n_chunks;
   for (int s = 0; s < nsweeps; ++s) {
-    k_pull_sweep<<<grid, kPullBlock, 0, c->stream>>>(a, (first_parity + s) & 1);
+    if (a.csr_val) k_pull_sweep<true><<<grid, kPullBlock, 0, c->stream>>>(a, (first_parity + s) & 1);
+    else k_pull_sweep<false><<<grid, kPullBlock, 0, c->stream>>>(a, (first_parity + s) & 1);
     k_pull_step<<<1, 256, 0, c->stream>>>(g->pull_partials, grid, c->ctrl, alpha);
   }
   HIP_TRY(hipGetLastError());

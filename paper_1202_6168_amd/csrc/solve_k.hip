@@ -134,20 +134,26 @@ __global__ void __launch_bounds__(kRedBlock) k_finalize(const double* partials, 
 // ---------------------------------------------------------------------------
 // Exact residual F = B + P H - H (the identity of equations defF/defH),
 // pulled over the transpose in FP64 and stored as FP32.
+// general: the weights sit on the links (wh = H, each in-link multiplies its
+// own weight); PageRank: every link of column i carries d / #out_i
 __global__ void k_refresh_wh(int64_t n, const int32_t* __restrict__ col_ptr,
-                             const double* __restrict__ h, double d, double* __restrict__ wh) {
+                             const double* __restrict__ h, double d, double* __restrict__ wh,
+                             int general) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
     int32_t k = col_ptr[i + 1] - col_ptr[i];
-    wh[i] = k > 0 ? d * h[i] / (double)k : 0.0;  // H_i spread over its column: p_ji H_i
+    if (general) wh[i] = h[i];
+    else wh[i] = k > 0 ? d * h[i] / (double)k : 0.0;  // H_i spread over its column: p_ji H_i
   }
 }
 
 // Exact residual B + P H - H: blocks [0, nl) take the rows with in-degree <=
 // kHeavyRow (8 lanes per row); blocks [nl, nl + n_chunks) sum one kHeavyChunk
 // piece of a heavy row each into chunk_sum
+template <bool W>
 __global__ void __launch_bounds__(kRedBlock) k_refresh_main(
     int64_t n, int nl, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ csr_col,
+    const double* __restrict__ csr_val,
     const double* __restrict__ wh, const double* __restrict__ b, const double* __restrict__ h,
     float* __restrict__ f, double* partials, const int32_t* __restrict__ chunk_beg,
     const int32_t* __restrict__ chunk_end, double* __restrict__ chunk_sum) {
@@ -163,7 +169,7 @@ __global__ void __launch_bounds__(kRedBlock) k_refresh_main(
       for (int u = 0; u < U; ++u) i[u] = e + u * kRedBlock < e1 ? csr_col[e + u * kRedBlock] : -1;
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (i[u] >= 0) acc += wh[i[u]];
+        if (i[u] >= 0) acc += W ? csr_val[e + u * kRedBlock] * wh[i[u]] : wh[i[u]];
     }
     block_reduce3<kRedBlock>(acc, unused, um);
     if (threadIdx.x == 0) chunk_sum[c] = acc;
@@ -180,7 +186,7 @@ __global__ void __launch_bounds__(kRedBlock) k_refresh_main(
       const int32_t e0 = row_ptr[j], e1 = row_ptr[j + 1];
       live = e1 - e0 <= kHeavyRow;
       if (live)
-        for (int32_t e = e0 + sub; e < e1; e += 8) acc += wh[csr_col[e]];
+        for (int32_t e = e0 + sub; e < e1; e += 8) acc += W ? csr_val[e] * wh[csr_col[e]] : wh[csr_col[e]];
     }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
@@ -656,7 +662,8 @@ int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const doub
 int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f,
                         double* wh, double* chunk_sum) {
   const int64_t n = g->n;
-  k_refresh_wh<<<grid_for(n, 256, 8192), 256, 0, c->stream>>>(n, g->col_ptr, h, g->d, wh);
+  const bool general = g->csr_val != nullptr;
+  k_refresh_wh<<<grid_for(n, 256, 8192), 256, 0, c->stream>>>(n, g->col_ptr, h, g->d, wh, general);
   HIP_TRY(hipGetLastError());
   // light rows and the heavy chunks in one launch, then the heavy rows from
   // their chunk sums (every sum in a fixed order)
@@ -664,9 +671,14 @@ int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const
   const int nf = g->n_heavy > 0 ? std::min(64, (g->n_heavy + kRedBlock - 1) / kRedBlock) : 0;
   const int nl = grid_for(n, kRedBlock / 8, cap - nf);
   const int nc = g->n_heavy > 0 ? g->n_chunks : 0;
-  k_refresh_main<<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, wh, b, h, f,
-                                                       c->partials, g->chunk_beg, g->chunk_end,
-                                                       chunk_sum);
+  if (general)
+    k_refresh_main<true><<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, g->csr_val,
+                                                               wh, b, h, f, c->partials, g->chunk_beg,
+                                                               g->chunk_end, chunk_sum);
+  else
+    k_refresh_main<false><<<nl + nc, kRedBlock, 0, c->stream>>>(n, nl, g->row_ptr, g->csr_col, nullptr,
+                                                                wh, b, h, f, c->partials, g->chunk_beg,
+                                                                g->chunk_end, chunk_sum);
   HIP_TRY(hipGetLastError());
   if (nf > 0) {
     k_refresh_heavy_fin<<<nf, kRedBlock, 0, c->stream>>>(g->n_heavy, g->heavy_rows, g->chunk_h,

@@ -122,6 +122,9 @@ _SIGNATURES = {
     "ditr_abort": ([_vp], _i32),
     "ditr_graph_create": ([_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _dbl,
                            ctypes.POINTER(Opts)], _i32),
+    "ditr_graph_create_weighted": ([_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _vp,
+                                    ctypes.POINTER(Opts)], _i32),
+    "ditr_graph_contraction": ([_vp, ctypes.POINTER(_dbl)], _i32),
     "ditr_graph_destroy": ([_vp], _i32),
     "ditr_graph_partitions": ([_vp, ctypes.POINTER(_i64), _vp, _i64], _i32),
     "ditr_partition": ([_vp, _i64, _i64, _vp, _vp, _i32, _i64, _vp], _i32),
@@ -258,9 +261,13 @@ class Context:
 
 
 class Graph:
-    """ditr_graph: borrows the CSC tensors (int32, on the context's device)."""
+    """ditr_graph: borrows the CSC tensors (int32, on the context's device).
 
-    def __init__(self, ctx: Context, col_ptr, row_idx, damping: float = 0.85, opts: Opts = None):
+    val (optional, float64, one weight per CSC entry): a general matrix
+    (ditr_graph_create_weighted); damping is then unused."""
+
+    def __init__(self, ctx: Context, col_ptr, row_idx, damping: float = 0.85, opts: Opts = None,
+                 val=None):
         torch = ctx.torch
         if col_ptr.dtype != torch.int32 or row_idx.dtype != torch.int32:
             raise TypeError("CSC arrays must be int32")
@@ -271,13 +278,29 @@ class Graph:
         self.row_idx = row_idx.contiguous()
         self.n = self.col_ptr.numel() - 1
         self.nnz = self.row_idx.numel()
+        self.val = None
         h = ctypes.c_void_p()
         o = opts if opts is not None else opts_default()
-        check(lib().ditr_graph_create(ctx.handle, ctypes.byref(h), self.n, self.nnz,
-                                      _ptr(self.col_ptr), _ptr(self.row_idx) if self.nnz else None,
-                                      damping, ctypes.byref(o)))
+        if val is not None:
+            if val.dtype != torch.float64 or not val.is_cuda or val.numel() != self.nnz:
+                raise TypeError("val must be a float64 device tensor with one entry per link")
+            self.val = val.contiguous()
+            check(lib().ditr_graph_create_weighted(ctx.handle, ctypes.byref(h), self.n, self.nnz,
+                                                   _ptr(self.col_ptr),
+                                                   _ptr(self.row_idx) if self.nnz else None,
+                                                   _ptr(self.val) if self.nnz else None,
+                                                   ctypes.byref(o)))
+        else:
+            check(lib().ditr_graph_create(ctx.handle, ctypes.byref(h), self.n, self.nnz,
+                                          _ptr(self.col_ptr), _ptr(self.row_idx) if self.nnz else None,
+                                          damping, ctypes.byref(o)))
         self.handle = h
         ctx._children.add(self)
+
+    def contraction(self) -> float:
+        c = ctypes.c_double()
+        check(lib().ditr_graph_contraction(self.handle, ctypes.byref(c)))
+        return c.value
 
     def partitions(self):
         import numpy as np
