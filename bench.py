@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="DITR_MODE_* (0 = default)")
+    ap.add_argument("--priority", action="store_true",
+                    help="normalized priority test |F_i| / ((#in_i + 1)(#out_i + 1)) > T")
+    ap.add_argument("--part-type", type=int, default=None, help="DITR_PART_* of the plan")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -288,14 +291,16 @@ def main():
     ctx = ditr.Context(0)
     t0 = time.perf_counter()
     cpt, rit = torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)
-    g = ditr.Graph(ctx, cpt, rit)
+    gopts = ditr.opts_default() if args.part_type is None else ditr.opts_default(part_type=args.part_type)
+    g = ditr.Graph(ctx, cpt, rit, opts=gopts)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t0)
     K = len(g.partitions()) - 1
     bt = torch.from_numpy(b).to(dev)
     ht = torch.empty(spec.n, dtype=torch.float64, device=dev)
     ft = torch.empty(spec.n, dtype=torch.float32, device=dev)
-    opts = ditr.opts_default(mode=args.mode, flags=ditr.FLAG_TIME_KERNELS)
+    opts = ditr.opts_default(mode=args.mode, flags=ditr.FLAG_TIME_KERNELS
+                             | (ditr.FLAG_PRIORITY if args.priority else 0))
 
     for _ in range(args.warmup):
         ditr.solve(ctx, g, bt, ht, ft, rel_tol=args.tol, opts=opts, allow=(ditr.OK,))
@@ -348,6 +353,8 @@ def main():
             "tol": args.tol,
             "mode": "partitioned sweep" if args.mode in (0, 3) else "mode %d" % args.mode,
             "partitions": K,
+            "part_type": int(gopts.part_type),
+            "priority_test": bool(args.priority),
         },
         "edges_per_step": edges / args.steps,
         "normalized_iterations": edges / args.steps / ri.size,

@@ -58,9 +58,11 @@ typedef struct ditr_graph ditr_graph; /* uploaded CSC + partition plan + transpo
 /* Node-set partition types (Section 2.3). */
 enum { DITR_PART_CB = 0,       /* cost-balanced: contiguous ranges of ~L/K out-links */
        DITR_PART_UNIFORM = 1,  /* contiguous ranges of floor(N/K) ids, last one takes the rest */
-       DITR_PART_CB_INOUT = 2  /* contiguous ranges of ~2L/K in+out links: a partition's whole
-                                  link cost, in the spirit of the alternative balance the
-                                  paper proposes after the CB rule */ };
+       DITR_PART_CB_INOUT = 2, /* contiguous ranges of ~2L/K in+out links: a partition's whole
+                                  link cost (a cheap proxy for the balance below) */
+       DITR_PART_PMASS = 3     /* the alternative balance the paper proposes after the CB rule:
+                                  equal internal p mass sum_{n,m in Omega_k} |p_nm| per block
+                                  (ditr_partition_pmass gives the exact rule) */ };
 
 /* Diffusion kernels. */
 enum { DITR_MODE_AUTO = 0,       /* = DITR_MODE_PARTITION */
@@ -104,6 +106,13 @@ typedef struct {
  * level even when every partition could stay resident in one cooperative
  * launch (the default whenever the partitions fit the device at once). */
 #define DITR_FLAG_NO_RESIDENT 2u
+/* opts.flags: in DITR_MODE_PARTITION, diffuse node i when its normalized
+ * priority |F_i| / ((#in_i + 1)(#out_i + 1)) exceeds T, the quantity whose
+ * argmax Section 2.4 names as the node choice, under the same cyclic threshold
+ * schedule (T_0, T /= alpha, no-pass rule on that ratio). Needs
+ * sum_i (#in_i + 1)(#out_i + 1) < 2^28 (DITR_EINVAL otherwise); other modes
+ * return DITR_EINVAL. */
+#define DITR_FLAG_PRIORITY 4u
 
 typedef struct {
   int64_t edges;       /* elementary edge diffusions (Section 2.4: normalized iterations x L) */
@@ -170,6 +179,18 @@ int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, i
  * the other types). Synchronizes for CB_INOUT (temporary in-link prefix). */
 int ditr_partition(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
                    const int32_t* d_row_idx, int part_type, int64_t K, int64_t* d_ptr);
+/* Partition of equal internal p mass (Section 2.3, the balance the paper
+ * proposes as possibly better than CB) into d_ptr (device int64, K+1
+ * boundaries, 1 <= K <= n). A link i -> t weighs floor(|p_ti| 2^32) integer
+ * units (p_ti = damping / #out_i, or d_val[e] for a general matrix: one weight
+ * per CSC entry, NULL for PageRank), so block masses are exact; the result is
+ * the contiguous K-block partition whose largest internal mass t* is smallest,
+ * each block taking from the left as many nodes as keep its mass <= t*
+ * (trailing boundaries n if fewer blocks cover the nodes). Also the plan of
+ * DITR_PART_PMASS. Synchronizes. */
+int ditr_partition_pmass(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+                         const int32_t* d_row_idx, const double* d_val, double damping, int64_t K,
+                         int64_t* d_ptr);
 
 /* ---- plain solve (steps: init, diffusion, transfer, residual, refresh) -- */
 /* Exact residual F = B + P H - H (identity of equations defF and defH):

@@ -145,6 +145,8 @@ int ditr_partition(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr
                    const int32_t* d_row_idx, int part_type, int64_t K, int64_t* d_ptr) {
   if (!c || !d_col_ptr || !d_ptr) return set_error(DITR_EINVAL, "NULL argument");
   if (n < 1 || K < 1 || K > n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
+  if (part_type == DITR_PART_PMASS)
+    return set_error(DITR_EINVAL, "the internal-mass partition needs the weights: use ditr_partition_pmass");
   if (part_type != DITR_PART_CB && part_type != DITR_PART_UNIFORM && part_type != DITR_PART_CB_INOUT)
     return set_error(DITR_EINVAL, "unknown partition type %d", part_type);
   if (part_type == DITR_PART_CB_INOUT && nnz > 0 && !d_row_idx)
@@ -159,6 +161,17 @@ int ditr_partition(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(in_prefix);
   return rc;
+}
+
+int ditr_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
+                         const int32_t* d_row_idx, const double* d_val, double damping, int64_t K,
+                         int64_t* d_ptr) {
+  if (!c || !d_col_ptr || !d_ptr || (nnz > 0 && !d_row_idx)) return set_error(DITR_EINVAL, "NULL argument");
+  if (n < 1 || K < 1 || K > n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(DITR_EINVAL, "nnz out of range");
+  if (!d_val && !(damping > 0 && damping < 1)) return set_error(DITR_EINVAL, "damping must lie in (0, 1)");
+  HIP_TRY(hipSetDevice(c->device));
+  return launch_partition_pmass(c, n, nnz, d_col_ptr, d_row_idx, d_val, damping, K, d_ptr, nullptr);
 }
 
 int ditr_graph_destroy(ditr_graph* g) {
@@ -207,7 +220,10 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
   HIP_TRY(hipMemsetAsync(g->part_lock, 0, sizeof(int) * K, c->stream));
   int64_t* tmp = nullptr;
   HIP_TRY(hipMalloc((void**)&tmp, sizeof(int64_t) * (K + 1)));
-  int rc = launch_partition(c, g->n, g->col_ptr, g->row_ptr, g->part_type, K, tmp, g->part_ptr);
+  int rc = g->part_type == DITR_PART_PMASS
+               ? launch_partition_pmass(c, g->n, g->nnz, g->col_ptr, g->row_idx, g->val, g->d, K, tmp,
+                                        g->part_ptr)
+               : launch_partition(c, g->n, g->col_ptr, g->row_ptr, g->part_type, K, tmp, g->part_ptr);
   hipError_t e = rc ? hipSuccess
                     : hipMemcpyAsync(g->part_ptr_host, tmp, sizeof(int64_t) * (K + 1),
                                      hipMemcpyDeviceToHost, c->stream);
@@ -238,7 +254,7 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
   ditr_opts_default(&o);
   if (opts) o = *opts;
   if (o.part_type != DITR_PART_CB && o.part_type != DITR_PART_UNIFORM &&
-      o.part_type != DITR_PART_CB_INOUT)
+      o.part_type != DITR_PART_CB_INOUT && o.part_type != DITR_PART_PMASS)
     return set_error(DITR_EINVAL, "unknown partition type %d", o.part_type);
   if (o.block == 0) o.block = 1024;
   if (o.block != 256 && o.block != 512 && o.block != 1024)
@@ -467,6 +483,21 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     return finish(set_error(DITR_EINVAL, "unknown mode %d", mode));
   if (noalloc && mode != DITR_MODE_PARTITION)
     return finish(set_error(DITR_EINVAL, "the allocation-free solve runs the partitioned sweep only"));
+  const bool prio = (o.flags & DITR_FLAG_PRIORITY) != 0;
+  if (prio && mode != DITR_MODE_PARTITION)
+    return finish(set_error(DITR_EINVAL, "the normalized priority test runs in the partitioned sweep"));
+  if (prio) {
+    // The partitioned sweep keeps T >= 2^-28 of the total fluid D (its fixed
+    // point). A level where no node passes has |F_i| <= T c_i for all i, so
+    // D <= T sum_i c_i; with sum_i c_i < 2^28 some node always passes at the
+    // lowest T, and the run cannot stall.
+    double csum = 0;
+    rc = launch_prio_sum(c, g, &csum);
+    if (rc) return finish(rc);
+    if (!(csum < 268435456.0))
+      return finish(set_error(DITR_EINVAL, "the normalized priority test needs sum (#in+1)(#out+1) < 2^28 "
+                              "(this graph: %.6g)", csum));
+  }
   if (noalloc && (o.flags & DITR_FLAG_TIME_KERNELS))
     return finish(set_error(DITR_EINVAL, "the allocation-free solve creates no timing events"));
   if (mode == DITR_MODE_ASYNC) {
@@ -586,14 +617,15 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
       bool resident = false;
       if (!(o.flags & DITR_FLAG_NO_RESIDENT)) {
-        rc = part_resident_fits(c, g, &resident);
+        rc = part_resident_fits(c, g, &resident, prio);
         if (rc) return finish(rc);
       }
       if (resident) {
         // every partition resident for the whole stage: one cooperative launch
         rc = t_begin();
         if (!rc) {
-          rc = launch_part_resident(c, g, sb, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30));
+          rc = launch_part_resident(c, g, sb, d_f, d_h, o.alpha, m, (int)std::min<int64_t>(budget, 1 << 30),
+                                    prio);
           if (rc == DITR_EHIP) {  // cooperative launch refused: relaunch per level instead
             (void)hipGetLastError();
             resident = false;
@@ -613,7 +645,7 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
       // rest of a batch into no-ops
       for (int64_t done_l = 0; !resident && done_l < budget; done_l += batch) {
         const uint64_t before = c->ctrl_host->sweeps;
-        rc = launch_part_sweeps(c, g, sb, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr);
+        rc = launch_part_sweeps(c, g, sb, d_f, d_h, o.alpha, m, batch, timed ? ev : nullptr, prio);
         if (!rc) rc = read_ctrl(c);
         if (!rc) rc = t_sum((int64_t)(c->ctrl_host->sweeps - before));
         if (rc) return finish(rc);

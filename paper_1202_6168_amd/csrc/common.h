@@ -245,6 +245,9 @@ int launch_col_abs(ditr_ctx* c, ditr_graph* g, double* h_max, int* h_bad);
 int launch_partition(ditr_ctx* c, int64_t n, const int32_t* col_ptr, const int32_t* row_ptr,
                      int part_type, int64_t K, int64_t* out64, int32_t* out32);
 int launch_in_prefix(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* row_idx, int32_t* out);
+int launch_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr,
+                           const int32_t* row_idx, const double* val, double d, int64_t K,
+                           int64_t* out64, int32_t* out32);
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);
@@ -263,14 +266,15 @@ int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out);
 int build_part_plan(ditr_ctx* c, ditr_graph* g);
 void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
-size_t part_lds_bytes(int nodes, int local_edges);
+size_t part_lds_bytes(int nodes, int local_edges, bool prio = false);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
                         double target, double T0);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
-                       double alpha, int m, int nlaunch, hipEvent_t* ev);
-int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits);
+                       double alpha, int m, int nlaunch, hipEvent_t* ev, bool prio);
+int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits, bool prio);
 int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
-                         double alpha, int m, int max_levels);
+                         double alpha, int m, int max_levels, bool prio);
+int launch_prio_sum(ditr_ctx* c, const ditr_graph* g, double* h_sum);
 int launch_zero_u64(ditr_ctx* c, unsigned long long* p, int64_t n);
 // static scratch of ditr_solve_noalloc (noalloc.hip): device address on the
 // context's device, looked up once per device at context creation

@@ -183,6 +183,8 @@ struct PartArgs {
   const int* abort_flag;  // host abort word (mapped)
   int n_heavy;
   int lds_nodes;   // node capacity of the LDS layout
+  int prio;        // 1: threshold test on |F_i| / c_i, c_i = (#in_i + 1)(#out_i + 1) (Section 2.4)
+  const int32_t* __restrict__ row_ptr;  // transpose row pointer (in-degrees, priority only)
   int lds_edges;   // local-target capacity (a larger partition reads its targets from memory)
   int max_levels;  // resident kernel: threshold levels before it returns
   float alpha;
@@ -244,6 +246,7 @@ struct PartView {
   int32_t* lptr;
   int32_t* odeg;
   uint32_t* lidx_words;
+  uint32_t* cq;     // priority: c_i = (#in_i + 1)(#out_i + 1), capped at 2^30
   const uint16_t* lidx;
   int lo, np, lbase, nl;
   bool lidx_in_lds;
@@ -256,7 +259,8 @@ __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* 
   v.dH = reinterpret_cast<float*>(smem + (size_t)cap * 8);
   v.lptr = reinterpret_cast<int32_t*>(smem + (size_t)cap * 12);
   v.odeg = reinterpret_cast<int32_t*>(smem + (size_t)cap * 16 + 4);
-  v.lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4);
+  v.cq = reinterpret_cast<uint32_t*>(smem + (size_t)cap * 20 + 4);
+  v.lidx_words = reinterpret_cast<uint32_t*>(smem + (size_t)cap * (a.prio ? 24 : 20) + 4);
   v.lo = a.part_ptr[p];
   v.np = a.part_ptr[p + 1] - v.lo;
   v.lbase = a.loc_ptr[v.lo];
@@ -271,7 +275,7 @@ __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* 
 // 1. load the partition into LDS: local CSC offsets in local order, fluid and
 // out-degrees in node order through inv (coalesced; eight nodes per thread in
 // flight)
-template <int BLOCK>
+template <int BLOCK, bool PRIO>
 __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
   const int tid = threadIdx.x;
   for (int i = tid; i < v.np; i += BLOCK) v.lptr[i] = a.loc_ptr[v.lo + i] - v.lbase;
@@ -298,6 +302,14 @@ __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
           v.odeg[r[u]] = c1[u] - c0[u];
         }
       }
+    }
+  }
+  if (PRIO) {
+    // the normalized priority's divisor (#in_i + 1)(#out_i + 1) of Section 2.4
+    for (int j = tid; j < v.np; j += BLOCK) {
+      const int32_t g = v.lo + j;
+      const long long in = a.row_ptr[g + 1] - a.row_ptr[g], out = a.col_ptr[g + 1] - a.col_ptr[g];
+      v.cq[a.inv[g]] = (uint32_t)min((in + 1) * (out + 1), 1LL << 30);
     }
   }
   if (tid == 0) v.lptr[v.np] = v.nl;
@@ -500,7 +512,7 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
 // and pushes its share to every local target with LDS atomics, eight targets
 // per step: their loads are issued together, then the adds. TARGETS_LDS: the local targets were copied to LDS (the pointer then has
 // a known address space and the loop waits on LDS traffic only).
-template <int BLOCK, bool TARGETS_LDS>
+template <int BLOCK, bool TARGETS_LDS, bool PRIO>
 __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quantum, double& edges,
                               double& diffs, int s0, int s1) {
   const uint16_t* __restrict__ lidx =
@@ -516,10 +528,12 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
       const int od = v.odeg[i];
       const int e0 = v.lptr[i], e1 = v.lptr[i + 1];
       const float dh = v.dH[i];
+      // priority: node i's own threshold T c_i in the same fixed point
+      const long long Ti = PRIO ? (long long)v.cq[i] << 32 : Tq;
       // keeps the compiler from sinking these reads into the branch below,
       // which would cost a second round trip for every node that passes
       asm volatile("" ::"v"(od), "v"(e0), "v"(e1), "v"(dh));
-      if (!(f > Tq || f < -Tq)) continue;
+      if (!(f > Ti || f < -Ti)) continue;
       // the fluid read leaves the node; what other threads push meanwhile
       // stays there (an atomic subtract, no returned value to wait for)
       add_fixed(&v.Fq[i], -f);
@@ -543,11 +557,11 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
   }
 }
 
-template <int BLOCK>
+template <int BLOCK, bool PRIO>
 __device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum, double& edges,
                             double& diffs, int s0, int s1) {
-  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true>(a, v, quantum, edges, diffs, s0, s1);
-  else part_sweeps_t<BLOCK, false>(a, v, quantum, edges, diffs, s0, s1);
+  if (v.lidx_in_lds) part_sweeps_t<BLOCK, true, PRIO>(a, v, quantum, edges, diffs, s0, s1);
+  else part_sweeps_t<BLOCK, false, PRIO>(a, v, quantum, edges, diffs, s0, s1);
 }
 
 // 4. H += dH and the shares p_i dH_i published for the outside targets, in node
@@ -555,7 +569,7 @@ __device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum
 // flight). Sums |F| plus the fluid in flight to outside targets into resid and
 // the largest |F| into fmx. RESIDENT: F stays in LDS and dH restarts from zero;
 // otherwise F goes back to memory.
-template <int BLOCK, bool RESIDENT>
+template <int BLOCK, bool RESIDENT, bool PRIO>
 __device__ void part_publish(const PartArgs& a, const PartView& v, double quantum, float* S_out,
                              double& resid, double& fmx) {
   constexpr int U = 8;
@@ -590,7 +604,8 @@ __device__ void part_publish(const PartArgs& a, const PartView& v, double quantu
       if (RESIDENT) st_agent(&S_out[g], so);
       else S_out[g] = so;
       resid += fabs(f);
-      fmx = fmax(fmx, fabs(f));
+      // largest priority (|F_i| / c_i under the normalized test)
+      fmx = fmax(fmx, PRIO ? fabs(f) / (double)v.cq[i] : fabs(f));
     }
   }
 }
@@ -637,7 +652,7 @@ __global__ void __launch_bounds__(256) k_part_items(PartArgs a, int parity) {
 //   4. writes F and H back and publishes S_out = p_i dH_i;
 //   5. the last workgroup to finish reduces the per-workgroup sums and sets
 //      the next T and the stop flag (no separate step kernel).
-template <int BLOCK>
+template <int BLOCK, bool PRIO>
 __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   if (__hip_atomic_load(&a.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const float* S_in = a.S + (size_t)(parity ^ 1) * a.n;
@@ -651,14 +666,14 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   const PartView v = part_view(a, smem, p);
 
   const double quantum = fixed_quantum(a.ctrl->T);
-  part_load<BLOCK>(a, v, 1.0 / quantum);
+  part_load<BLOCK, PRIO>(a, v, 1.0 / quantum);
   part_inflow<BLOCK, false>(a, v, p, S_in, 1.0 / quantum, 0, 0);
   double edges = 0, diffs = 0;
-  part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 0, a.m);
+  part_sweeps<BLOCK, PRIO>(a, v, quantum, edges, diffs, 0, a.m);
 
   // ---- 4. write back, publish p_i dH_i, partial sums
   double resid = 0, fmx = 0;
-  part_publish<BLOCK, false>(a, v, quantum, S_out, resid, fmx);
+  part_publish<BLOCK, false, PRIO>(a, v, quantum, S_out, resid, fmx);
 
   // ---- 5. per-workgroup sums; the last workgroup finishes the launch
   block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
@@ -746,7 +761,7 @@ __device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err,
 // level parity: a workgroup publishes level l only after every workgroup has
 // finished level l-1, so nobody still reads the level l-2 contents it
 // replaces. F goes back to memory when the stage ends.
-template <int BLOCK>
+template <int BLOCK, bool PRIO>
 __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_limit) {
   const int tid = threadIdx.x;
   constexpr int NW = BLOCK / 64;
@@ -763,7 +778,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   double edges_tail = 0, diffs_tail = 0;  // own counts of the last level, added at the end
 
   double quantum = fixed_quantum(T);
-  part_load<BLOCK>(a, v, 1.0 / quantum);
+  part_load<BLOCK, PRIO>(a, v, 1.0 / quantum);
   // wave w of workgroup p takes item units w K + p, (w + NW) K + p, ..., so
   // the densest units (packed first) are spread over all CUs; the sources of
   // the first one and of the first light links are loaded at the end of the
@@ -789,7 +804,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     if (unit0 < a.n_units) unit_gather<true>(S_in, L0, iv);
     light_gather(S_in, lsrc, lv);
     double edges = 0, diffs = 0;
-    part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 0, 1);
+    part_sweeps<BLOCK, PRIO>(a, v, quantum, edges, diffs, 0, 1);
     // the sums of level l-1, in flight while the outside fluid is added
     const double* prev = a.partials + (size_t)(par ^ 1) * a.K * kStride;
     double D = 0, M = 0, E = 0, P = 0;
@@ -822,11 +837,11 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
       if (P == 0 && M / a.alpha < Tn) Tn = M / a.alpha;
       Tn = fmax(Tn, D * kPartTFloor);
     }
-    part_sweeps<BLOCK>(a, v, quantum, edges, diffs, 1, a.m);
+    part_sweeps<BLOCK, PRIO>(a, v, quantum, edges, diffs, 1, a.m);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
     double resid = 0, fmx = 0;
-    part_publish<BLOCK, true>(a, v, quantum, S_out, resid, fmx);
+    part_publish<BLOCK, true, PRIO>(a, v, quantum, S_out, resid, fmx);
     double* part = a.partials + (size_t)par * a.K * kStride;
     block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
     edges_tail = edges;
@@ -1169,6 +1184,35 @@ int launch_zero_u64(ditr_ctx* c, unsigned long long* p, int64_t n) {
   return DITR_OK;
 }
 
+// sum over nodes of (#in_i + 1)(#out_i + 1) in FP64, one partial per block
+__global__ void __launch_bounds__(256) k_prio_sum(int64_t n, const int32_t* __restrict__ col_ptr,
+                                                  const int32_t* __restrict__ row_ptr, double* partial) {
+  double s = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+    s += (double)(row_ptr[i + 1] - row_ptr[i] + 1) * (double)(col_ptr[i + 1] - col_ptr[i] + 1);
+  s = wave_sum(s);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Synchronizes.
+int launch_prio_sum(ditr_ctx* c, const ditr_graph* g, double* h_sum) {
+  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (g->n + 255) / 256));
+  if ((size_t)nb * 4 > c->partials_cap * 4) return set_error(DITR_EINVAL, "partials too small");
+  k_prio_sum<<<nb, 256, 0, c->stream>>>(g->n, g->col_ptr, g->row_ptr, c->partials);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> part(nb);
+  HIP_TRY(hipMemcpyAsync(part.data(), c->partials, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double s = 0;
+  for (double x : part) s += x;
+  *h_sum = s;
+  return DITR_OK;
+}
+
 SolveBufs graph_bufs(const ditr_graph* g) {
   ditr_graph* m = const_cast<ditr_graph*>(g);
   SolveBufs b;
@@ -1216,26 +1260,32 @@ int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, d
 
 // LDS of a partition workgroup: 20 bytes per node (+4) and 2 bytes per local
 // target slot (two spare slots let the targets move as aligned 32-bit words)
-size_t part_lds_bytes(int nodes, int local_edges) {
-  return (size_t)nodes * 20 + 4 + (size_t)local_edges * 2 + 16;
+size_t part_lds_bytes(int nodes, int local_edges, bool prio) {
+  return (size_t)nodes * (prio ? 24 : 20) + 4 + (size_t)local_edges * 2 + 16;
 }
 
 // dynamic LDS both partition kernels may take (the larger static part counts)
 int part_configure(ditr_ctx* c) {
-  hipFuncAttributes as, ar;
-  if (hipFuncGetAttributes(&as, reinterpret_cast<const void*>(&k_part_sweep<kPB>)) != hipSuccess ||
-      hipFuncGetAttributes(&ar, reinterpret_cast<const void*>(&k_part_resident<kPB>)) != hipSuccess) {
-    (void)hipGetLastError();
-    return set_error(DITR_EHIP, "hipFuncGetAttributes failed");
+  const void* fns[] = {reinterpret_cast<const void*>(&k_part_sweep<kPB, false>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, false>),
+                       reinterpret_cast<const void*>(&k_part_sweep<kPB, true>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, true>)};
+  size_t stat = 0;
+  for (const void* fn : fns) {
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(DITR_EHIP, "hipFuncGetAttributes failed");
+    }
+    stat = std::max(stat, at.sharedSizeBytes);
   }
-  const size_t stat = std::max(as.sharedSizeBytes, ar.sharedSizeBytes);
   for (size_t total : {c->lds_per_cu, c->lds_per_block}) {
     if (total <= stat + 64) continue;
     const size_t dyn = total - stat;
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_sweep<kPB>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_resident<kPB>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess) {
+    bool ok = true;
+    for (const void* fn : fns)
+      ok = ok && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess;
+    if (ok) {
       c->part_lds_dyn = dyn;
       return DITR_OK;
     }
@@ -1247,7 +1297,7 @@ int part_configure(ditr_ctx* c) {
 
 namespace {
 int part_args(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h, double alpha,
-              int m, PartArgs* out, size_t* lds) {
+              int m, bool prio, PartArgs* out, size_t* lds) {
   const PartPlan& q = g->pp;
   PartArgs a;
   a.n = g->n;
@@ -1280,27 +1330,29 @@ int part_args(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, d
   a.abort_flag = c->abort_dev;
   a.n_heavy = q.n_heavy;
   a.lds_nodes = std::max(1, g->max_part);
+  a.prio = prio ? 1 : 0;
+  a.row_ptr = g->row_ptr;
   a.max_levels = 0;
   a.alpha = (float)alpha;
   a.d = (float)g->d;
   a.dd = g->d;
-  if (part_lds_bytes(a.lds_nodes, 0) > c->part_lds_dyn)
+  if (part_lds_bytes(a.lds_nodes, 0, prio) > c->part_lds_dyn)
     return set_error(DITR_EINVAL, "partition of %d nodes needs %zu B of LDS (limit %zu)", a.lds_nodes,
-                     part_lds_bytes(a.lds_nodes, 0), c->part_lds_dyn);
+                     part_lds_bytes(a.lds_nodes, 0, prio), c->part_lds_dyn);
   // local targets go to LDS when the largest partition's fit beside its nodes
-  const int64_t room = ((int64_t)c->part_lds_dyn - (int64_t)part_lds_bytes(a.lds_nodes, 0)) / 2;
+  const int64_t room = ((int64_t)c->part_lds_dyn - (int64_t)part_lds_bytes(a.lds_nodes, 0, prio)) / 2;
   a.lds_edges = (int)std::max<int64_t>(0, std::min<int64_t>(room, (int64_t)q.max_local_edges + 2));
-  *lds = part_lds_bytes(a.lds_nodes, a.lds_edges);
+  *lds = part_lds_bytes(a.lds_nodes, a.lds_edges, prio);
   *out = a;
   return DITR_OK;
 }
 }  // namespace
 
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
-                       double alpha, int m, int nlaunch, hipEvent_t* ev) {
+                       double alpha, int m, int nlaunch, hipEvent_t* ev, bool prio) {
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, sb, f, h, alpha, m, &a, &lds);
+  int rc = part_args(c, g, sb, f, h, alpha, m, prio, &a, &lds);
   if (rc) return rc;
   const PartPlan& q = g->pp;
   for (int s = 0; s < nlaunch; ++s) {
@@ -1308,7 +1360,8 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, fl
     if (units > 0)
       k_part_items<<<(unsigned)std::min<int64_t>((units + 3) / 4, 16384), 256, 0, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s], c->stream));
-    k_part_sweep<kPB><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+    if (prio) k_part_sweep<kPB, true><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+    else k_part_sweep<kPB, false><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s + 1], c->stream));
   }
   HIP_TRY(hipGetLastError());
@@ -1317,14 +1370,16 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, fl
 
 // Whether every partition workgroup of g can be resident at once (one
 // cooperative launch of K workgroups).
-int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits) {
+int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits, bool prio) {
   *fits = false;
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, graph_bufs(g), nullptr, nullptr, 1.5, 1, &a, &lds);
+  int rc = part_args(c, g, graph_bufs(g), nullptr, nullptr, 1.5, 1, prio, &a, &lds);
   if (rc) return rc;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB>, kPB, lds) != hipSuccess) {
+  const hipError_t oe = prio ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB, true>, kPB, lds)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB, false>, kPB, lds);
+  if (oe != hipSuccess) {
     (void)hipGetLastError();
     return DITR_OK;
   }
@@ -1333,10 +1388,10 @@ int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits) {
 }
 
 int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,
-                         double alpha, int m, int max_levels) {
+                         double alpha, int m, int max_levels, bool prio) {
   PartArgs a;
   size_t lds = 0;
-  int rc = part_args(c, g, sb, f, h, alpha, m, &a, &lds);
+  int rc = part_args(c, g, sb, f, h, alpha, m, prio, &a, &lds);
   if (rc) return rc;
   a.max_levels = max_levels;
   // epochs of this launch's levels: above every flag an earlier launch stored
@@ -1355,7 +1410,9 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, 
   int spin_limit = 1 << 24;
   if (const char* e = getenv("DITR_SPIN_LIMIT")) spin_limit = std::max(0, std::min(atoi(e), 1 << 24));
   void* args[] = {&a, &spin_limit};
-  HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_part_resident<kPB>), dim3(a.K),
+  HIP_TRY(hipLaunchCooperativeKernel(prio ? reinterpret_cast<const void*>(&k_part_resident<kPB, true>)
+                                          : reinterpret_cast<const void*>(&k_part_resident<kPB, false>),
+                                     dim3(a.K),
                                      dim3(kPB), args, (unsigned)lds, c->stream));
   return DITR_OK;
 }

@@ -253,7 +253,7 @@ bool read_cache(const char* path, std::vector<Entry>& out) {
     en.default_seconds = num("default_seconds", 0);
     if (!(en.alpha > 1) || !(en.refresh_at >= 0) || en.part_nodes < 0 || en.m < 0 ||
         (en.part_type != DITR_PART_CB && en.part_type != DITR_PART_UNIFORM &&
-         en.part_type != DITR_PART_CB_INOUT))
+         en.part_type != DITR_PART_CB_INOUT && en.part_type != DITR_PART_PMASS))
       continue;
     out.push_back(en);
   }
@@ -360,7 +360,7 @@ int ditr_tune_cache_put(const char* path, uint64_t key, const ditr_opts* o, doub
   if (!path || !o) return set_error(DITR_EINVAL, "NULL argument");
   if (!(o->alpha > 1) || !(o->refresh_at >= 0) || o->part_nodes < 0 || o->sweeps_per_claim < 0 ||
       (o->part_type != DITR_PART_CB && o->part_type != DITR_PART_UNIFORM &&
-       o->part_type != DITR_PART_CB_INOUT))
+       o->part_type != DITR_PART_CB_INOUT && o->part_type != DITR_PART_PMASS))
     return set_error(DITR_EINVAL, "options out of range");
   Entry e;
   e.key = key;
@@ -469,8 +469,8 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
   };
 
   // stage 1: partition plan (type x nodes per partition; 0 = the library's choice)
-  const int types_all[3] = {DITR_PART_CB_INOUT, DITR_PART_CB, DITR_PART_UNIFORM};
-  const int ntypes = effort == 0 ? 1 : 3;
+  const int types_all[4] = {DITR_PART_CB_INOUT, DITR_PART_CB, DITR_PART_UNIFORM, DITR_PART_PMASS};
+  const int ntypes = effort == 0 ? 1 : 4;
   const int sizes[6] = {0, 1024, 2048, 3072, 6144, 8192};
   for (int ti = 0; ti < ntypes; ++ti)
     for (int s : sizes) {

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libditr.so")
 
 OK, NOT_CONVERGED, ABORTED, NOT_FOUND = 0, 1, 2, 3
 EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
-PART_CB, PART_UNIFORM, PART_CB_INOUT = 0, 1, 2
+PART_CB, PART_UNIFORM, PART_CB_INOUT, PART_PMASS = 0, 1, 2, 3
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
 FLAG_NO_RESIDENT = 2
+FLAG_PRIORITY = 4
 GNN_PARAMS = 9409
 GNN_ACT_X, GNN_ACT_PX, GNN_ACT_H1, GNN_ACT_PH1, GNN_ACT_H2 = 0, 1, 2, 3, 4
 
@@ -128,6 +129,7 @@ _SIGNATURES = {
     "ditr_graph_destroy": ([_vp], _i32),
     "ditr_graph_partitions": ([_vp, ctypes.POINTER(_i64), _vp, _i64], _i32),
     "ditr_partition": ([_vp, _i64, _i64, _vp, _vp, _i32, _i64, _vp], _i32),
+    "ditr_partition_pmass": ([_vp, _i64, _i64, _vp, _vp, _vp, _dbl, _i64, _vp], _i32),
     "ditr_residual": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)], _i32),
     "ditr_solve": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
                     ctypes.POINTER(Stats)], _i32),
@@ -330,6 +332,15 @@ def partition(ctx: Context, col_ptr, part_type: int, K: int, out, row_idx=None):
     check(lib().ditr_partition(ctx.handle, col_ptr.numel() - 1, nnz, _ptr(col_ptr),
                                _ptr(row_idx) if row_idx is not None else None, part_type, K,
                                _ptr(out)))
+    return out
+
+
+def partition_pmass(ctx: Context, col_ptr, row_idx, K: int, out, val=None, damping: float = 0.85):
+    """ditr_partition_pmass: K+1 boundaries of equal internal p mass (int64 device tensor `out`)."""
+    nnz = row_idx.numel()
+    check(lib().ditr_partition_pmass(ctx.handle, col_ptr.numel() - 1, nnz, _ptr(col_ptr),
+                                     _ptr(row_idx) if nnz else None,
+                                     _ptr(val) if val is not None else None, damping, K, _ptr(out)))
     return out
 
 
