@@ -169,6 +169,31 @@ int ditr_graph_create_weighted(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64
  * general one (0 when it has no links). */
 int ditr_graph_contraction(const ditr_graph* g, double* c_out);
 int ditr_graph_destroy(ditr_graph* g);
+/* ---- caller-owned workspaces ------------------------------------------- */
+/* Device bytes a call needs from a caller-provided workspace (an upper bound
+ * computed from the sizes alone):
+ *   nrhs = 0:  ditr_graph_upload_csc of a PageRank graph of n nodes and nnz
+ *              links with opts' partition type (NULL = defaults); the plan's
+ *              every table and temporary (transpose, partition tables, work
+ *              arrays of the solve and the exact residual) lies in it;
+ *   nrhs = R:  ditr_solve_batched with R right-hand sides (multiple of 4,
+ *              4..256): published shares, gathered inflow, activity flags,
+ *              heavy-row sums, per-right-hand-side thresholds and partials.
+ * Host-only (no device work). */
+int ditr_workspace_bytes(ditr_ctx* ctx, int64_t n, int64_t nnz, int nrhs, const ditr_opts* opts,
+                         size_t* bytes);
+/* ditr_graph_create with every device table carved from d_workspace (device,
+ * 256-byte aligned, ws_bytes long, owned by the caller, which must keep it
+ * until ditr_graph_destroy): the library allocates no device memory for the
+ * graph. DITR_ENOMEM if the workspace is too small (ditr_workspace_bytes with
+ * nrhs = 0 always suffices; ditr_graph_workspace_used tells what a graph
+ * took). PageRank matrices only. Synchronizes. */
+int ditr_graph_upload_csc(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64_t nnz,
+                          const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
+                          void* d_workspace, size_t ws_bytes, const ditr_opts* opts);
+/* Workspace bytes an uploaded graph actually used (0 for ditr_graph_create). */
+int ditr_graph_workspace_used(const ditr_graph* g, size_t* used);
+
 /* Number of partitions K of the plan and, if h_ptr != NULL and cap >= K+1,
  * the boundaries omega_0 = 0 < ... <= omega_K = n. Synchronizes. */
 int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, int64_t cap);
@@ -239,13 +264,15 @@ size_t ditr_noalloc_scratch_bytes(void);
  * Section 2.2 in X = d Q X + (1-d) V). Node-major layouts with row stride nrhs:
  * d_b FP64 [n][nrhs] (read), d_h FP64 [n][nrhs] (out: H, starts from 0),
  * d_f FP32 [n][nrhs] (out: exact residual rounded to FP32). Every right-hand
- * side has its own threshold T_r; all share each in-link read. per_rhs
- * (nullable, [nrhs]) gets each right-hand side's residual, ||B_r||_1 and
- * diffused edges; total (nullable) the sums and timing. Allocates a workspace
- * of about 8 nrhs n bytes for the call. Synchronizes. */
+ * side has its own threshold T_r; all share each in-link read. d_workspace
+ * (device, ws_bytes >= ditr_workspace_bytes(.., nrhs, ..), owned by the
+ * caller) holds the solve's buffers, about 12 nrhs n bytes; NULL lets the call
+ * allocate and free them itself. per_rhs (nullable, [nrhs]) gets each
+ * right-hand side's residual, ||B_r||_1 and diffused edges; total (nullable)
+ * the sums and timing. Synchronizes. */
 int ditr_solve_batched(ditr_ctx* ctx, const ditr_graph* g, int nrhs, const double* d_b,
                        double* d_h, float* d_f, double rel_tol, const ditr_opts* opts,
-                       ditr_stats* per_rhs, ditr_stats* total);
+                       void* d_workspace, size_t ws_bytes, ditr_stats* per_rhs, ditr_stats* total);
 
 /* ---- autotuner (step: partition size and threshold schedule) ----------- */
 typedef struct {

@@ -180,22 +180,11 @@ int ditr_graph_destroy(ditr_graph* g) {
   // whole device rather than the context's stream
   (void)hipSetDevice(g->device);
   (void)hipDeviceSynchronize();
-  (void)hipFree(g->row_ptr);
-  (void)hipFree(g->csr_col);
-  (void)hipFree(g->csr_val);
-  (void)hipFree(g->colabs);
-  (void)hipFree(g->heavy_rows);
-  (void)hipFree(g->chunk_h);
-  (void)hipFree(g->chunk_beg);
-  (void)hipFree(g->chunk_end);
-  (void)hipFree(g->chunk_sum);
-  (void)hipFree(g->pull_s);
-  (void)hipFree(g->pull_heavy);
-  (void)hipFree(g->pull_partials);
-  (void)hipFree(g->wh);
-  (void)hipFree(g->part_ptr);
-  (void)hipFree(g->part_T);
-  (void)hipFree(g->part_lock);
+  for (void* p : {(void*)g->row_ptr, (void*)g->csr_col, (void*)g->csr_val, (void*)g->colabs,
+                  (void*)g->heavy_rows, (void*)g->chunk_h, (void*)g->chunk_beg, (void*)g->chunk_end,
+                  (void*)g->chunk_sum, (void*)g->pull_s, (void*)g->pull_heavy, (void*)g->pull_partials,
+                  (void*)g->wh, (void*)g->part_ptr, (void*)g->part_T, (void*)g->part_lock})
+    g_free(g, p);
   delete[] g->part_ptr_host;
   free_part_plan(g);
   delete g;
@@ -204,9 +193,9 @@ int ditr_graph_destroy(ditr_graph* g) {
 
 // (re)build the partition plan with K parts; reads the boundaries back
 static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
-  (void)hipFree(g->part_ptr);
-  (void)hipFree(g->part_T);
-  (void)hipFree(g->part_lock);
+  g_free(g, g->part_ptr);
+  g_free(g, g->part_T);
+  g_free(g, g->part_lock);
   g->part_ptr = nullptr;
   g->part_T = nullptr;
   g->part_lock = nullptr;
@@ -214,21 +203,21 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
   g->part_ptr_host = new (std::nothrow) int64_t[K + 1];
   if (!g->part_ptr_host) return set_error(DITR_ENOMEM, "host allocation failed");
   g->K = K;
-  HIP_TRY(hipMalloc((void**)&g->part_ptr, sizeof(int32_t) * (K + 1)));
-  HIP_TRY(hipMalloc((void**)&g->part_T, sizeof(double) * K));
-  HIP_TRY(hipMalloc((void**)&g->part_lock, sizeof(int) * K));
+  HIP_TRY(g_alloc(g, (void**)&g->part_ptr, sizeof(int32_t) * (K + 1)));
+  HIP_TRY(g_alloc(g, (void**)&g->part_T, sizeof(double) * K));
+  HIP_TRY(g_alloc(g, (void**)&g->part_lock, sizeof(int) * K));
   HIP_TRY(hipMemsetAsync(g->part_lock, 0, sizeof(int) * K, c->stream));
   int64_t* tmp = nullptr;
-  HIP_TRY(hipMalloc((void**)&tmp, sizeof(int64_t) * (K + 1)));
+  HIP_TRY(g_alloc(g, (void**)&tmp, sizeof(int64_t) * (K + 1)));
   int rc = g->part_type == DITR_PART_PMASS
                ? launch_partition_pmass(c, g->n, g->nnz, g->col_ptr, g->row_idx, g->val, g->d, K, tmp,
-                                        g->part_ptr)
+                                        g->part_ptr, g)
                : launch_partition(c, g->n, g->col_ptr, g->row_ptr, g->part_type, K, tmp, g->part_ptr);
   hipError_t e = rc ? hipSuccess
                     : hipMemcpyAsync(g->part_ptr_host, tmp, sizeof(int64_t) * (K + 1),
                                      hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp);
+  g_free(g, tmp);
   if (rc) return rc;
   HIP_TRY(e);
   int64_t mx = 0;
@@ -243,7 +232,8 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
 // or a general matrix (one weight per CSC entry, Section 2).
 static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
                              const int32_t* d_col_ptr, const int32_t* d_row_idx, const double* d_val,
-                             double damping, const ditr_opts* opts) {
+                             double damping, const ditr_opts* opts, void* d_workspace = nullptr,
+                             size_t ws_bytes = 0) {
   if (!c || !out) return set_error(DITR_EINVAL, "NULL argument");
   *out = nullptr;
   if (n < 1 || n >= ((int64_t)1 << 31) - 1) return set_error(DITR_EINVAL, "n = %lld out of range", (long long)n);
@@ -280,13 +270,17 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
   g->row_idx = d_row_idx;
   g->val = nnz > 0 ? d_val : nullptr;
   g->part_type = o.part_type;
-  bool ok = hipMalloc((void**)&g->row_ptr, sizeof(int32_t) * (n + 1)) == hipSuccess &&
-            hipMalloc((void**)&g->csr_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) == hipSuccess &&
-            hipMalloc((void**)&g->heavy_rows, sizeof(int32_t) * n) == hipSuccess &&
-            hipMalloc((void**)&g->wh, sizeof(double) * n) == hipSuccess;
+  if (d_workspace) {
+    g->arena.base = static_cast<unsigned char*>(d_workspace);
+    g->arena.cap = ws_bytes;
+  }
+  bool ok = g_alloc(g, (void**)&g->row_ptr, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+            g_alloc(g, (void**)&g->csr_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) == hipSuccess &&
+            g_alloc(g, (void**)&g->heavy_rows, sizeof(int32_t) * n) == hipSuccess &&
+            g_alloc(g, (void**)&g->wh, sizeof(double) * n) == hipSuccess;
   if (ok && g->val)
-    ok = hipMalloc((void**)&g->csr_val, sizeof(double) * nnz) == hipSuccess &&
-         hipMalloc((void**)&g->colabs, sizeof(double) * n) == hipSuccess;
+    ok = g_alloc(g, (void**)&g->csr_val, sizeof(double) * nnz) == hipSuccess &&
+         g_alloc(g, (void**)&g->colabs, sizeof(double) * n) == hipSuccess;
   if (!ok) {
     ditr_graph_destroy(g);
     return set_error(DITR_ENOMEM, "device allocation failed (graph of n = %lld)", (long long)n);
@@ -337,7 +331,14 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
     K = std::max<int64_t>((n + 4095) / 4096, std::min<int64_t>(c->num_cus, n / 256));
   }
   K = std::max<int64_t>(1, std::min<int64_t>(K, n));
+  const size_t plan_mark = g->arena.used;  // each plan attempt reuses the same workspace
   for (int attempt = 0;; ++attempt) {
+    if (g->arena.base) {
+      g->arena.used = plan_mark;
+      g->part_ptr = nullptr;
+      g->part_T = nullptr;
+      g->part_lock = nullptr;
+    }
     rc = make_plan(c, g, K);
     if (rc) {
       ditr_graph_destroy(g);
@@ -375,6 +376,43 @@ int ditr_graph_create_weighted(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t
   if (nnz > 0 && !d_val) return set_error(DITR_EINVAL, "NULL weight array");
   static const double kNoLinks = 0.0;
   return graph_create_impl(c, out, n, nnz, d_col_ptr, d_row_idx, nnz > 0 ? d_val : &kNoLinks, 0.0, opts);
+}
+
+int ditr_workspace_bytes(ditr_ctx* c, int64_t n, int64_t nnz, int nrhs, const ditr_opts* opts,
+                         size_t* bytes) {
+  if (!c || !bytes) return set_error(DITR_EINVAL, "NULL argument");
+  if (n < 1 || nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(DITR_EINVAL, "sizes out of range");
+  ditr_opts o;
+  ditr_opts_default(&o);
+  if (opts) o = *opts;
+  if (nrhs == 0) {
+    *bytes = graph_workspace_bound(c, n, nnz, o.part_type, n);
+    return DITR_OK;
+  }
+  if (nrhs < 4 || nrhs > 256 || nrhs % 4)
+    return set_error(DITR_EINVAL, "nrhs must be 0 (graph upload) or a multiple of 4 in [4, 256]");
+  *bytes = batch_workspace_bytes(c, n, std::min<int64_t>(n, nnz / (kHeavyRow + 1) + 1), nrhs);
+  return DITR_OK;
+}
+
+int ditr_graph_upload_csc(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
+                          const int32_t* d_col_ptr, const int32_t* d_row_idx, double damping,
+                          void* d_workspace, size_t ws_bytes, const ditr_opts* opts) {
+  if (!d_workspace || ws_bytes == 0) return set_error(DITR_EINVAL, "NULL workspace");
+  if (((uintptr_t)d_workspace) % 256) return set_error(DITR_EINVAL, "workspace must be 256-byte aligned");
+  (void)workspace_overflow(true);
+  const int rc = graph_create_impl(c, out, n, nnz, d_col_ptr, d_row_idx, nullptr, damping, opts, d_workspace,
+                                   ws_bytes);
+  if (rc != DITR_OK && workspace_overflow(true))
+    return set_error(DITR_ENOMEM, "the workspace of %zu bytes is too small for this graph "
+                     "(ditr_workspace_bytes gives an upper bound)", ws_bytes);
+  return rc;
+}
+
+int ditr_graph_workspace_used(const ditr_graph* g, size_t* used) {
+  if (!g || !used) return set_error(DITR_EINVAL, "NULL argument");
+  *used = g->arena.base ? g->arena.peak : 0;
+  return DITR_OK;
 }
 
 int ditr_graph_contraction(const ditr_graph* g, double* c_out) {
@@ -719,8 +757,8 @@ int ditr_solve(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
 }
 
 int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double* d_b, double* d_h,
-                       float* d_f, double rel_tol, const ditr_opts* opts, ditr_stats* per_rhs,
-                       ditr_stats* total) {
+                       float* d_f, double rel_tol, const ditr_opts* opts, void* d_workspace,
+                       size_t ws_bytes, ditr_stats* per_rhs, ditr_stats* total) {
   const double t0 = now_s();
   if (!c || !g || !d_b || !d_h || !d_f) return set_error(DITR_EINVAL, "NULL argument");
   if (!(rel_tol >= 0) || !std::isfinite(rel_tol)) return set_error(DITR_EINVAL, "rel_tol must be >= 0");
@@ -740,7 +778,7 @@ int ditr_solve_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double*
   if (c->ctrl_host->err) return set_error(DITR_ENONFINITE, "B holds NaN or Inf");
   ditr_stats tot;
   memset(&tot, 0, sizeof(tot));
-  rc = batch_solve(c, g, nrhs, d_b, d_h, d_f, rel_tol, o, per_rhs, &tot);
+  rc = batch_solve(c, g, nrhs, d_b, d_h, d_f, rel_tol, o, per_rhs, &tot, d_workspace, ws_bytes);
   tot.seconds = now_s() - t0;
   tot.status = rc;
   if (total) *total = tot;

@@ -534,21 +534,57 @@ struct BatchWork {
   double* lane = nullptr;   // T, tol, b1, resid, edges: 5 x R doubles
   int* flags = nullptr;     // done[R], all_done, remaining
   unsigned long long* sweeps = nullptr;
+  unsigned char* ws = nullptr;  // caller workspace the buffers are carved from (nothing to free)
+  size_t ws_cap = 0, ws_used = 0;
 };
 
 static void free_work(BatchWork& w) {
-  for (void* p : {(void*)w.S, (void*)w.G, (void*)w.act, (void*)w.heavy_in, (void*)w.racc, (void*)w.part, (void*)w.lane,
-                  (void*)w.flags, (void*)w.sweeps})
-    (void)hipFree(p);
+  if (!w.ws)
+    for (void* p : {(void*)w.S, (void*)w.G, (void*)w.act, (void*)w.heavy_in, (void*)w.racc, (void*)w.part,
+                    (void*)w.lane, (void*)w.flags, (void*)w.sweeps})
+      (void)hipFree(p);
   w = BatchWork();
 }
 
+// one buffer of the batched solve: carved from the caller's workspace when
+// there is one, else hipMalloc
+static hipError_t work_alloc(BatchWork& w, void** p, size_t bytes) {
+  if (!w.ws) return hipMalloc(p, bytes);
+  const size_t need = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+  if (w.ws_used + need > w.ws_cap) return hipErrorOutOfMemory;
+  *p = w.ws + w.ws_used;
+  w.ws_used += need;
+  return hipSuccess;
+}
+
+static int batch_blocks(const ditr_ctx* c, int64_t n) {
+  return (int)std::min<int64_t>((int64_t)c->num_cus * 8, (n + 3) / 4);
+}
+
+// device bytes of the batched solve's buffers (the workspace ditr_solve_batched takes)
+size_t batch_workspace_bytes(const ditr_ctx* c, int64_t n, int64_t n_heavy, int R) {
+  auto al = [](size_t x) { return (std::max<size_t>(x, 1) + 255) & ~(size_t)255; };
+  const size_t N = (size_t)n, r = (size_t)R, nh = (size_t)std::max<int64_t>(1, n_heavy);
+  const size_t nb = (size_t)batch_blocks(c, n);
+  return al(sizeof(float) * 2 * N * r) + al(sizeof(float) * N * r) + al(2 * N) + al(sizeof(float) * nh * r) +
+         al(sizeof(double) * nh * r) + al(sizeof(double) * (nb + kFinBlocks + kStepBlocks) * r * 2) +
+         al(sizeof(double) * 5 * r) + al(sizeof(int) * (r + 3)) + al(sizeof(unsigned long long));
+}
+
 int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, double* d_h, float* d_f,
-                double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total) {
+                double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total,
+                void* d_workspace, size_t ws_bytes) {
   if (R < 4 || R > kMaxR || R % 4) return set_error(DITR_EINVAL, "nrhs must be a multiple of 4 in [4, 256]");
   const int64_t n = g->n;
-  const int nblocks = (int)std::min<int64_t>((int64_t)c->num_cus * 8, (n + 3) / 4);
+  const int nblocks = batch_blocks(c, n);
   BatchWork w;
+  if (d_workspace) {
+    const size_t need = batch_workspace_bytes(c, n, g->n_heavy, R);
+    if (ws_bytes < need)
+      return set_error(DITR_EINVAL, "batched workspace of %zu bytes is too small (%zu needed)", ws_bytes, need);
+    w.ws = static_cast<unsigned char*>(d_workspace);
+    w.ws_cap = ws_bytes;
+  }
   // the loop is captured as a graph, which the legacy null stream cannot do:
   // run on the context's private stream once the caller's stream has drained
   hipStream_t st = c->work;
@@ -564,17 +600,17 @@ int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, doub
     if (_e != hipSuccess)                                                                    \
       return fail(set_error(DITR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e)));      \
   } while (0)
-  B_TRY(hipMalloc((void**)&w.S, sizeof(float) * 2 * n * R));
-  B_TRY(hipMalloc((void**)&w.G, sizeof(float) * n * R));
-  B_TRY(hipMalloc((void**)&w.act, 2 * n));
-  B_TRY(hipMalloc((void**)&w.heavy_in, sizeof(float) * std::max(1, g->n_heavy) * R));
-  B_TRY(hipMalloc((void**)&w.racc, sizeof(double) * std::max(1, g->n_heavy) * R));
+  B_TRY(work_alloc(w, (void**)&w.S, sizeof(float) * 2 * n * R));
+  B_TRY(work_alloc(w, (void**)&w.G, sizeof(float) * n * R));
+  B_TRY(work_alloc(w, (void**)&w.act, 2 * n));
+  B_TRY(work_alloc(w, (void**)&w.heavy_in, sizeof(float) * std::max(1, g->n_heavy) * R));
+  B_TRY(work_alloc(w, (void**)&w.racc, sizeof(double) * std::max(1, g->n_heavy) * R));
   B_TRY(hipMemsetAsync(w.racc, 0, sizeof(double) * std::max(1, g->n_heavy) * R, st));
-  B_TRY(hipMalloc((void**)&w.part, sizeof(double) * (nblocks + kFinBlocks + kStepBlocks) * R * 2));
+  B_TRY(work_alloc(w, (void**)&w.part, sizeof(double) * (nblocks + kFinBlocks + kStepBlocks) * R * 2));
   B_TRY(hipMemsetAsync(w.part, 0, sizeof(double) * (nblocks + kFinBlocks + kStepBlocks) * R * 2, st));
-  B_TRY(hipMalloc((void**)&w.lane, sizeof(double) * 5 * R));
-  B_TRY(hipMalloc((void**)&w.flags, sizeof(int) * (R + 3)));
-  B_TRY(hipMalloc((void**)&w.sweeps, sizeof(unsigned long long)));
+  B_TRY(work_alloc(w, (void**)&w.lane, sizeof(double) * 5 * R));
+  B_TRY(work_alloc(w, (void**)&w.flags, sizeof(int) * (R + 3)));
+  B_TRY(work_alloc(w, (void**)&w.sweeps, sizeof(unsigned long long)));
   B_TRY(hipMemsetAsync(w.lane, 0, sizeof(double) * 5 * R, st));
   B_TRY(hipMemsetAsync(w.flags, 0, sizeof(int) * (R + 3), st));
   B_TRY(hipMemsetAsync(w.sweeps, 0, sizeof(unsigned long long), st));

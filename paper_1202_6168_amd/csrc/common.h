@@ -78,8 +78,20 @@ struct PartPlan {
   int64_t n_local = 0, n_ext = 0, n_heavy_edges = 0;
 };
 
+// Device memory of a graph's tables: hipMalloc'd buffer by buffer
+// (ditr_graph_create), or carved in order from a workspace the caller owns
+// (ditr_graph_upload_csc), in which case nothing is freed before the caller
+// releases the workspace.
+struct DevArena {
+  unsigned char* base = nullptr;  // caller workspace (nullptr: hipMalloc)
+  size_t cap = 0;
+  size_t used = 0;
+  size_t peak = 0;
+};
+
 struct ditr_graph {
   ditr_ctx* ctx = nullptr;
+  DevArena arena;
   int device = 0;                    // device of the context it was created on
   int64_t n = 0, nnz = 0;
   double d = 0.85;
@@ -131,6 +143,16 @@ struct SolveBufs {
   int64_t* epoch = nullptr;                   // host: item-word epochs handed out so far
 };
 SolveBufs graph_bufs(const ditr_graph* g);
+
+// allocation of a graph's device tables (arena.hip): from its workspace when
+// it has one (256-byte aligned, hipErrorOutOfMemory when it is full), else
+// hipMalloc; g_free releases a hipMalloc'd buffer and ignores workspace ones
+hipError_t g_alloc(ditr_graph* g, void** p, size_t bytes);
+void g_free(ditr_graph* g, void* p);
+bool workspace_overflow(bool reset);  // whether a workspace allocation failed on this thread
+// upper bound of the workspace a graph upload needs (ditr_workspace_bytes)
+size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part_type, int64_t K_max);
+size_t batch_workspace_bytes(const ditr_ctx* c, int64_t n, int64_t n_heavy, int R);
 
 // ---- error reporting (api.hip) ------------------------------------------
 int set_error(int code, const char* fmt, ...);
@@ -247,7 +269,8 @@ int launch_partition(ditr_ctx* c, int64_t n, const int32_t* col_ptr, const int32
 int launch_in_prefix(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* row_idx, int32_t* out);
 int launch_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr,
                            const int32_t* row_idx, const double* val, double d, int64_t K,
-                           int64_t* out64, int32_t* out32);
+                           int64_t* out64, int32_t* out32, ditr_graph* g = nullptr);
+size_t pmass_temp_bytes(int64_t n, int64_t nnz);
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);
@@ -262,7 +285,7 @@ int launch_pull_prepare(ditr_ctx* c, const ditr_graph* g);
 int launch_pull_sweeps(ditr_ctx* c, const ditr_graph* g, float* f, double* h, double alpha,
                        int first_parity, int nsweeps);
 int build_heavy_chunks(ditr_ctx* c, ditr_graph* g);
-int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out);
+int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out, ditr_graph* g = nullptr);
 int build_part_plan(ditr_ctx* c, ditr_graph* g);
 void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
@@ -300,7 +323,8 @@ int persistent_static_lds_impl(int block, size_t* bytes);
 int persistent_configure(ditr_ctx* c, size_t cu_lds, size_t block_lds);
 
 int batch_solve(ditr_ctx* c, const ditr_graph* g, int R, const double* d_b, double* d_h, float* d_f,
-                double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total);
+                double rel_tol, const ditr_opts& o, ditr_stats* per_rhs, ditr_stats* total,
+                void* d_workspace, size_t ws_bytes);
 
 // host driver of the plain solve (api.hip)
 int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h, float* d_f, int warm,

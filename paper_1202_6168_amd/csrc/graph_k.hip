@@ -205,17 +205,18 @@ int launch_validate_csc(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_
   return DITR_OK;
 }
 
-int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out) {
+int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out, ditr_graph* g) {
   int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   if (ntiles < 1) ntiles = 1;
   int32_t* sums = nullptr;
-  HIP_TRY(hipMalloc((void**)&sums, sizeof(int32_t) * ntiles));
+  HIP_TRY(g ? g_alloc(g, (void**)&sums, sizeof(int32_t) * ntiles) : hipMalloc((void**)&sums, sizeof(int32_t) * ntiles));
   k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(in, n, sums);
   k_scan_sums<<<1, kScanBlock, 0, c->stream>>>(sums, ntiles);
   k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, c->stream>>>(in, n, sums, out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(sums);
+  if (g) g_free(g, sums);
+  else (void)hipFree(sums);
   HIP_TRY(e);
   if (n == 0) HIP_TRY(hipMemsetAsync(out, 0, sizeof(int32_t), c->stream));
   return DITR_OK;
@@ -224,12 +225,12 @@ int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out) 
 int launch_build_transpose(ditr_ctx* c, ditr_graph* g) {
   const int64_t n = g->n, nnz = g->nnz;
   int32_t* cnt = nullptr;
-  HIP_TRY(hipMalloc((void**)&cnt, sizeof(int32_t) * (n + 1)));
+  HIP_TRY(g_alloc(g, (void**)&cnt, sizeof(int32_t) * (n + 1)));
   k_zero_i32<<<grid_for(n + 1, kBlock), kBlock, 0, c->stream>>>(cnt, n + 1);
   if (nnz > 0) k_count_in<<<grid_for(nnz, kBlock), kBlock, 0, c->stream>>>(nnz, g->row_idx, cnt);
-  int rc = scan_exclusive_i32(c, cnt, n, g->row_ptr);
+  int rc = scan_exclusive_i32(c, cnt, n, g->row_ptr, g);
   if (rc) {
-    (void)hipFree(cnt);
+    g_free(g, cnt);
     return rc;
   }
   // cnt becomes the fill cursor
@@ -247,7 +248,7 @@ int launch_build_transpose(ditr_ctx* c, ditr_graph* g) {
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&hc, hcount, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(cnt);
+  g_free(g, cnt);
   HIP_TRY(e);
   g->n_heavy = hc;
   return DITR_OK;

@@ -904,8 +904,6 @@ __global__ void k_gather_ranges(int32_t nh, const int32_t* __restrict__ rows,
 
 }  // namespace
 
-// exclusive scan (graph_k.hip)
-int scan_exclusive_i32(ditr_ctx* c, const int32_t* in, int64_t n, int32_t* out);
 
 void free_part_plan(ditr_graph* g) {
   PartPlan& q = g->pp;
@@ -914,7 +912,7 @@ void free_part_plan(ditr_graph* g) {
                   (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.item_row, (void*)q.part_items,
                   (void*)q.unit_src, (void*)q.unit_meta, (void*)q.item_word,
                   (void*)q.S, (void*)q.partials, (void*)q.counters, (void*)q.inv})
-    (void)hipFree(p);
+    g_free(g, p);
   q = PartPlan();
 }
 
@@ -928,10 +926,10 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   int32_t *cnt = nullptr, *cnt2 = nullptr, *light_ptr = nullptr, *heavy_ptr = nullptr;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(st);
-    (void)hipFree(cnt);
-    (void)hipFree(cnt2);
-    (void)hipFree(light_ptr);
-    (void)hipFree(heavy_ptr);
+    g_free(g, cnt);
+    g_free(g, cnt2);
+    g_free(g, light_ptr);
+    g_free(g, heavy_ptr);
   };
 #define PP_TRY(expr)                                                                     \
   do {                                                                                   \
@@ -942,35 +940,35 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     }                                                                                    \
   } while (0)
   if (g->max_part > 65536) return set_error(DITR_EINVAL, "partitions above 65536 nodes");
-  PP_TRY(hipMalloc((void**)&q.pid, sizeof(int32_t) * n));
-  PP_TRY(hipMalloc((void**)&q.loc_ptr, sizeof(int32_t) * (n + 1)));
-  PP_TRY(hipMalloc((void**)&cnt, sizeof(int32_t) * (n + 1)));
-  PP_TRY(hipMalloc((void**)&cnt2, sizeof(int32_t) * (n + 1)));
-  PP_TRY(hipMalloc((void**)&light_ptr, sizeof(int32_t) * (n + 1)));
-  PP_TRY(hipMalloc((void**)&heavy_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(g_alloc(g, (void**)&q.pid, sizeof(int32_t) * n));
+  PP_TRY(g_alloc(g, (void**)&q.loc_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(g_alloc(g, (void**)&cnt, sizeof(int32_t) * (n + 1)));
+  PP_TRY(g_alloc(g, (void**)&cnt2, sizeof(int32_t) * (n + 1)));
+  PP_TRY(g_alloc(g, (void**)&light_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(g_alloc(g, (void**)&heavy_ptr, sizeof(int32_t) * (n + 1)));
   const int gb = grid_for(n, 256, 8192);
   const int gw = grid_for(n * 64, 256, 16384);  // one wave per row
   k_fill_pid<<<std::min(K, 8192), 256, 0, st>>>(K, g->part_ptr, q.pid);
   k_count_local<<<gb, 256, 0, st>>>(n, g->col_ptr, g->row_idx, q.pid, cnt);
   PP_TRY(hipGetLastError());
-  int rc = scan_exclusive_i32(c, cnt, n, q.loc_ptr);
+  int rc = scan_exclusive_i32(c, cnt, n, q.loc_ptr, g);
   if (rc) { cleanup(); return rc; }
   int32_t nloc = 0;
   PP_TRY(hipMemcpy(&nloc, q.loc_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
-  PP_TRY(hipMalloc((void**)&q.loc_idx, sizeof(uint16_t) * (nloc + 4)));  // word copies may overrun by one
+  PP_TRY(g_alloc(g, (void**)&q.loc_idx, sizeof(uint16_t) * (nloc + 4)));  // word copies may overrun by one
   k_fill_local<<<gb, 256, 0, st>>>(n, g->col_ptr, g->row_idx, q.pid, g->part_ptr, q.loc_ptr, q.loc_idx);
   k_count_ext<<<gw, 256, 0, st>>>(n, g->row_ptr, g->csr_col, q.pid, cnt, cnt2);
   PP_TRY(hipGetLastError());
-  rc = scan_exclusive_i32(c, cnt, n, light_ptr);
-  if (!rc) rc = scan_exclusive_i32(c, cnt2, n, heavy_ptr);
+  rc = scan_exclusive_i32(c, cnt, n, light_ptr, g);
+  if (!rc) rc = scan_exclusive_i32(c, cnt2, n, heavy_ptr, g);
   if (rc) { cleanup(); return rc; }
   int32_t nlight = 0, nheavy_e = 0;
   PP_TRY(hipMemcpy(&nlight, light_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
   PP_TRY(hipMemcpy(&nheavy_e, heavy_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
-  PP_TRY(hipMalloc((void**)&q.ext_src, sizeof(int32_t) * std::max(1, nlight)));
-  PP_TRY(hipMalloc((void**)&q.ext_row, sizeof(uint16_t) * std::max(1, nlight)));
-  PP_TRY(hipMalloc((void**)&q.heavy_src, sizeof(int32_t) * std::max(1, nheavy_e)));
-  PP_TRY(hipMalloc((void**)&q.ext_ptr, sizeof(int32_t) * (K + 1)));
+  PP_TRY(g_alloc(g, (void**)&q.ext_src, sizeof(int32_t) * std::max(1, nlight)));
+  PP_TRY(g_alloc(g, (void**)&q.ext_row, sizeof(uint16_t) * std::max(1, nlight)));
+  PP_TRY(g_alloc(g, (void**)&q.heavy_src, sizeof(int32_t) * std::max(1, nheavy_e)));
+  PP_TRY(g_alloc(g, (void**)&q.ext_ptr, sizeof(int32_t) * (K + 1)));
   k_fill_ext<<<gw, 256, 0, st>>>(n, g->row_ptr, g->csr_col, q.pid, g->part_ptr, light_ptr, heavy_ptr,
                                  q.ext_src, q.ext_row, q.heavy_src);
   k_gather_ptr<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, g->part_ptr, light_ptr, q.ext_ptr);
@@ -978,7 +976,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   // heavy rows (sorted) and their chunks; per-partition ranges of the heavy list
   int* hcount = &c->ctrl->err;
   PP_TRY(hipMemsetAsync(hcount, 0, sizeof(int), st));
-  PP_TRY(hipMalloc((void**)&q.heavy_rows, sizeof(int32_t) * std::max<int64_t>(1, n)));
+  PP_TRY(g_alloc(g, (void**)&q.heavy_rows, sizeof(int32_t) * std::max<int64_t>(1, n)));
   k_heavy_list<<<gb, 256, 0, st>>>(n, heavy_ptr, q.heavy_rows, hcount);
   int nh = 0;
   PP_TRY(hipMemcpyAsync(&nh, hcount, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1060,7 +1058,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     }
     q.n_units = (int32_t)nu;
     auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
-      HIP_TRY(hipMalloc((void**)dst, sizeof(int32_t) * std::max<size_t>(1, v.size())));
+      HIP_TRY(g_alloc(g, (void**)dst, sizeof(int32_t) * std::max<size_t>(1, v.size())));
       if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
       return DITR_OK;
     };
@@ -1069,32 +1067,32 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
     if (!urc) urc = up(&q.unit_src, usrc);
     if (!urc) urc = up(&q.unit_meta, umeta);
     if (urc) { cleanup(); return urc; }
-    PP_TRY(hipMalloc((void**)&q.item_word, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
+    PP_TRY(g_alloc(g, (void**)&q.item_word, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
     PP_TRY(hipMemset(q.item_word, 0, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
     // the unit table replaces the per-row source list
-    PP_TRY(hipFree(q.heavy_src));
+    g_free(g, q.heavy_src);
     q.heavy_src = nullptr;
   }
   q.n_heavy = nh;
-  PP_TRY(hipMalloc((void**)&q.part_heavy, sizeof(int32_t) * (K + 1)));
+  PP_TRY(g_alloc(g, (void**)&q.part_heavy, sizeof(int32_t) * (K + 1)));
   PP_TRY(hipMemcpy(q.part_heavy, ph.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice));
-  PP_TRY(hipMalloc((void**)&q.pw, sizeof(float) * n));
-  PP_TRY(hipMalloc((void**)&q.ext_deg, sizeof(int32_t) * n));
+  PP_TRY(g_alloc(g, (void**)&q.pw, sizeof(float) * n));
+  PP_TRY(g_alloc(g, (void**)&q.ext_deg, sizeof(int32_t) * n));
   k_weights<<<gb, 256, 0, st>>>(n, g->col_ptr, q.loc_ptr, (float)g->d, q.pw, q.ext_deg);
   PP_TRY(hipGetLastError());
-  PP_TRY(hipMalloc((void**)&q.S, sizeof(float) * 2 * n));
-  PP_TRY(hipMalloc((void**)&q.counters, sizeof(int) * kCounters));
+  PP_TRY(g_alloc(g, (void**)&q.S, sizeof(float) * 2 * n));
+  PP_TRY(g_alloc(g, (void**)&q.counters, sizeof(int) * kCounters));
   PP_TRY(hipMemset(q.counters, 0, sizeof(int) * kCounters));
-  PP_TRY(hipMalloc((void**)&q.partials, sizeof(double) * kStride * 2 * K));
+  PP_TRY(g_alloc(g, (void**)&q.partials, sizeof(double) * kStride * 2 * K));
   {
     std::vector<int32_t> lp(K + 1);
     int32_t* d_lp = nullptr;
-    PP_TRY(hipMalloc((void**)&d_lp, sizeof(int32_t) * (K + 1)));
+    PP_TRY(g_alloc(g, (void**)&d_lp, sizeof(int32_t) * (K + 1)));
     k_gather_ptr<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, g->part_ptr, q.loc_ptr, d_lp);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(lp.data(), d_lp, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d_lp);
+    g_free(g, d_lp);
     PP_TRY(e);
     int32_t mx = 0;
     for (int k = 0; k < K; ++k) mx = std::max(mx, lp[k + 1] - lp[k]);
@@ -1126,7 +1124,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
       const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
       for (int64_t r = 0; r < hi - lo; ++r) inv[lo + ord[lo + r]] = (uint16_t)r;
     }
-    PP_TRY(hipMalloc((void**)&q.inv, sizeof(uint16_t) * std::max<int64_t>(1, n)));
+    PP_TRY(g_alloc(g, (void**)&q.inv, sizeof(uint16_t) * std::max<int64_t>(1, n)));
     PP_TRY(hipMemcpy(q.inv, inv.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
     {
       std::vector<uint16_t> li((size_t)nloc + 4), li2((size_t)nloc + 4, 0);

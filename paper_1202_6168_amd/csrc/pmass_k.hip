@@ -186,17 +186,23 @@ int grid_for(int64_t n, int block, int cap) {
 // (device). val = nullptr: PageRank weights d / #out_i. Synchronizes.
 int launch_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr,
                            const int32_t* row_idx, const double* val, double d, int64_t K,
-                           int64_t* out64, int32_t* out32) {
+                           int64_t* out64, int32_t* out32, ditr_graph* g) {
   hipStream_t st = c->stream;
   std::vector<void*> owned;
+  // temporaries: the graph's own memory when there is a graph (its workspace
+  // for an uploaded one), else hipMalloc
   auto alloc = [&](void** p, size_t bytes) -> bool {
-    if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+    bytes = std::max<size_t>(bytes, 16);
+    if ((g ? g_alloc(g, p, bytes) : hipMalloc(p, bytes)) != hipSuccess) return false;
     owned.push_back(*p);
     return true;
   };
   auto done = [&](int rc) {
     (void)hipStreamSynchronize(st);
-    for (void* p : owned) (void)hipFree(p);
+    for (void* p : owned) {
+      if (g) g_free(g, p);
+      else (void)hipFree(p);
+    }
     return rc;
   };
   const size_t L = (size_t)std::max<int64_t>(nnz, 1);
@@ -280,4 +286,21 @@ int launch_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* c
   k_pm_probe<<<1, kProbeBlock, 0, st>>>(n, K, key1, S, gbeg, tc, nb, out64, out32);
   if (hipGetLastError() != hipSuccess) return done(set_error(DITR_EHIP, "internal-mass boundaries failed"));
   return done(DITR_OK);
+}
+
+// device bytes launch_partition_pmass takes for its temporaries (an upper
+// bound, with the radix sort's and the scan's own scratch)
+size_t pmass_temp_bytes(int64_t n, int64_t nnz) {
+  auto al = [](size_t x) { return (std::max<size_t>(x, 16) + 255) & ~(size_t)255; };
+  const size_t L = (size_t)std::max<int64_t>(nnz, 1);
+  size_t tb = 0, sb = 0;
+  if (nnz > 0) {
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                             (unsigned long long*)nullptr, (unsigned long long*)nullptr, (int)nnz,
+                                             0, 63);
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, sb, (unsigned long long*)nullptr,
+                                           (unsigned long long*)nullptr, (int)nnz);
+  }
+  return 4 * al(8 * L) + al(8 * (L + 1)) + al(4 * ((size_t)n + 1)) + 2 * al(8 * kProbes) + al(8) + al(tb) +
+         al(sb) + 4096;
 }

@@ -237,7 +237,7 @@ int build_heavy_chunks(ditr_ctx* c, ditr_graph* g) {
     std::sort(rows.begin(), rows.end());
     HIP_TRY(hipMemcpyAsync(g->heavy_rows, rows.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice,
                            c->stream));
-    HIP_TRY(hipMalloc((void**)&d_ranges, sizeof(int32_t) * 2 * nh));
+    HIP_TRY(g_alloc(g, (void**)&d_ranges, sizeof(int32_t) * 2 * nh));
     k_gather_heavy_ranges<<<std::min(1024, (nh + 255) / 256), 256, 0, c->stream>>>(
         nh, g->heavy_rows, g->row_ptr, d_ranges);
     hipError_t e = hipGetLastError();
@@ -245,7 +245,7 @@ int build_heavy_chunks(ditr_ctx* c, ditr_graph* g) {
       e = hipMemcpyAsync(ranges.data(), d_ranges, sizeof(int32_t) * 2 * nh, hipMemcpyDeviceToHost,
                          c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(d_ranges);
+    g_free(g, d_ranges);
     HIP_TRY(e);
   }
   std::vector<int32_t> ch, cb, ce;
@@ -257,18 +257,18 @@ int build_heavy_chunks(ditr_ctx* c, ditr_graph* g) {
     }
   g->n_chunks = (int32_t)ch.size();
   const size_t nc = std::max<size_t>(1, ch.size());
-  HIP_TRY(hipMalloc((void**)&g->chunk_h, sizeof(int32_t) * nc));
-  HIP_TRY(hipMalloc((void**)&g->chunk_beg, sizeof(int32_t) * nc));
-  HIP_TRY(hipMalloc((void**)&g->chunk_end, sizeof(int32_t) * nc));
+  HIP_TRY(g_alloc(g, (void**)&g->chunk_h, sizeof(int32_t) * nc));
+  HIP_TRY(g_alloc(g, (void**)&g->chunk_beg, sizeof(int32_t) * nc));
+  HIP_TRY(g_alloc(g, (void**)&g->chunk_end, sizeof(int32_t) * nc));
   if (!ch.empty()) {
     HIP_TRY(hipMemcpy(g->chunk_h, ch.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->chunk_beg, cb.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(g->chunk_end, ce.data(), sizeof(int32_t) * ch.size(), hipMemcpyHostToDevice));
   }
-  HIP_TRY(hipMalloc((void**)&g->chunk_sum, sizeof(double) * nc));
-  HIP_TRY(hipMalloc((void**)&g->pull_s, sizeof(float) * 2 * g->n));
-  HIP_TRY(hipMalloc((void**)&g->pull_heavy, sizeof(double) * 2 * std::max(1, nh)));
-  HIP_TRY(hipMalloc((void**)&g->pull_partials,
+  HIP_TRY(g_alloc(g, (void**)&g->chunk_sum, sizeof(double) * nc));
+  HIP_TRY(g_alloc(g, (void**)&g->pull_s, sizeof(float) * 2 * g->n));
+  HIP_TRY(g_alloc(g, (void**)&g->pull_heavy, sizeof(double) * 2 * std::max(1, nh)));
+  HIP_TRY(g_alloc(g, (void**)&g->pull_partials,
                     sizeof(double) * kStride * (light_blocks(c, g->n) + std::max(1, g->n_chunks))));
   return DITR_OK;
 }

@@ -137,7 +137,12 @@ _SIGNATURES = {
                             ctypes.POINTER(Stats)], _i32),
     "ditr_noalloc_scratch_bytes": ([], ctypes.c_size_t),
     "ditr_solve_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
-                            _vp, ctypes.POINTER(Stats)], _i32),
+                            _vp, ctypes.c_size_t, _vp, ctypes.POINTER(Stats)], _i32),
+    "ditr_workspace_bytes": ([_vp, _i64, _i64, _i32, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)],
+                             _i32),
+    "ditr_graph_upload_csc": ([_vp, ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _dbl, _vp, ctypes.c_size_t,
+                               ctypes.POINTER(Opts)], _i32),
+    "ditr_graph_workspace_used": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _i32),
     "ditr_tune": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _dbl, _i32, ctypes.c_char_p,
                    ctypes.POINTER(Opts), ctypes.POINTER(TuneInfo)], _i32),
     "ditr_tune_key": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _dbl,
@@ -262,14 +267,29 @@ class Context:
             pass
 
 
+def workspace_bytes(ctx: Context, n: int, nnz: int, nrhs: int = 0, opts: Opts = None) -> int:
+    """ditr_workspace_bytes: device bytes of a graph upload (nrhs = 0) or of a
+    batched solve with nrhs right-hand sides."""
+    b = ctypes.c_size_t()
+    check(lib().ditr_workspace_bytes(ctx.handle, n, nnz, nrhs, ctypes.byref(opts) if opts else None,
+                                     ctypes.byref(b)))
+    return b.value
+
+
 class Graph:
     """ditr_graph: borrows the CSC tensors (int32, on the context's device).
 
     val (optional, float64, one weight per CSC entry): a general matrix
-    (ditr_graph_create_weighted); damping is then unused."""
+    (ditr_graph_create_weighted); damping is then unused.
+    workspace (optional, uint8 device tensor of at least workspace_bytes(ctx,
+    n, nnz) bytes): every device table of the graph lives in it
+    (ditr_graph_upload_csc) and the library allocates nothing for the graph.
+
+    Batched solves on this graph keep their workspace in a tensor cached on
+    the graph per right-hand-side count, so repeated solves allocate nothing."""
 
     def __init__(self, ctx: Context, col_ptr, row_idx, damping: float = 0.85, opts: Opts = None,
-                 val=None):
+                 val=None, workspace=None):
         torch = ctx.torch
         if col_ptr.dtype != torch.int32 or row_idx.dtype != torch.int32:
             raise TypeError("CSC arrays must be int32")
@@ -281,9 +301,21 @@ class Graph:
         self.n = self.col_ptr.numel() - 1
         self.nnz = self.row_idx.numel()
         self.val = None
+        self.workspace = None
+        self._batch_ws = {}
         h = ctypes.c_void_p()
         o = opts if opts is not None else opts_default()
-        if val is not None:
+        if workspace is not None:
+            if val is not None:
+                raise ValueError("a workspace upload takes PageRank graphs")
+            if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+                raise TypeError("workspace must be a contiguous uint8 device tensor")
+            self.workspace = workspace
+            check(lib().ditr_graph_upload_csc(ctx.handle, ctypes.byref(h), self.n, self.nnz,
+                                              _ptr(self.col_ptr),
+                                              _ptr(self.row_idx) if self.nnz else None, damping,
+                                              _ptr(workspace), workspace.numel(), ctypes.byref(o)))
+        elif val is not None:
             if val.dtype != torch.float64 or not val.is_cuda or val.numel() != self.nnz:
                 raise TypeError("val must be a float64 device tensor with one entry per link")
             self.val = val.contiguous()
@@ -298,6 +330,20 @@ class Graph:
                                           damping, ctypes.byref(o)))
         self.handle = h
         ctx._children.add(self)
+
+    def workspace_used(self) -> int:
+        u = ctypes.c_size_t()
+        check(lib().ditr_graph_workspace_used(self.handle, ctypes.byref(u)))
+        return u.value
+
+    def batch_workspace(self, R: int):
+        """The uint8 device tensor ditr_solve_batched works in for R right-hand sides."""
+        ws = self._batch_ws.get(R)
+        if ws is None:
+            nb = workspace_bytes(self.ctx, self.n, self.nnz, R)
+            ws = self.ctx.torch.empty(nb, dtype=self.ctx.torch.uint8, device=self.col_ptr.device)
+            self._batch_ws = {R: ws}  # one cached size at a time
+        return ws
 
     def contraction(self) -> float:
         c = ctypes.c_double()
@@ -393,8 +439,9 @@ def noalloc_scratch_bytes() -> int:
 
 
 def solve_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, opts: Opts = None,
-                  allow=(OK, NOT_CONVERGED, ABORTED)):
-    """ditr_solve_batched: node-major [n, R] right-hand sides; returns (total, per_rhs)."""
+                  allow=(OK, NOT_CONVERGED, ABORTED), workspace=None):
+    """ditr_solve_batched: node-major [n, R] right-hand sides; returns (total, per_rhs).
+    The solve works in `workspace` (uint8 device tensor) or in the graph's cached one."""
     torch = ctx.torch
     if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
         raise TypeError("b, h must be float64 and f float32")
@@ -407,9 +454,10 @@ def solve_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, opts: 
     per = (Stats * R)()
     tot = Stats()
     o = opts if opts is not None else opts_default()
+    ws = workspace if workspace is not None else g.batch_workspace(R)
     rc = lib().ditr_solve_batched(ctx.handle, g.handle, R, _ptr(b), _ptr(h), _ptr(f), rel_tol,
-                                  ctypes.byref(o), ctypes.cast(per, ctypes.c_void_p),
-                                  ctypes.byref(tot))
+                                  ctypes.byref(o), _ptr(ws), ws.numel(),
+                                  ctypes.cast(per, ctypes.c_void_p), ctypes.byref(tot))
     check(rc, allow)
     return tot, list(per)
 
