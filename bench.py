@@ -57,9 +57,17 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", type=int, default=0, help="DITR_MODE_* (0 = default)")
+    ap.add_argument("--alpha", type=float, default=None, help="threshold divisor (default: library's)")
     ap.add_argument("--priority", action="store_true",
                     help="normalized priority test |F_i| / ((#in_i + 1)(#out_i + 1)) > T")
     ap.add_argument("--part-type", type=int, default=None, help="DITR_PART_* of the plan")
+    ap.add_argument("--large", action="store_true",
+                    help="the 5e7-node graph (same generator, seed 3) instead of the 1e6-node one")
+    ap.add_argument("--n", type=int, default=None,
+                    help="nodes of the generated graph (default: the 1e6-node workload)")
+    ap.add_argument("--block", type=int, default=None, help="locality block of the generator")
+    ap.add_argument("--part-nodes", type=int, default=0, help="nodes per partition (0: library)")
+    ap.add_argument("--warm-epochs", type=int, default=40, help="training epochs of the warm start")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,7 +189,7 @@ def batched_bench(ctx, g, n, dev):
     }
 
 
-def warm_bench(ctx, dev):
+def warm_bench(ctx, dev, epochs=40):
     """Train the warm-start network, then cold vs learned start on unseen graphs."""
     import numpy as np
     import torch
@@ -204,7 +212,6 @@ def warm_bench(ctx, dev):
         train.append((keep, g, y, w))
     t_labels = time.perf_counter() - t0
     net = ditr.Gnn(ctx, block=1000, seed=7)
-    epochs = 40
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ep in range(epochs):
@@ -237,7 +244,7 @@ def warm_bench(ctx, dev):
             t0 = time.perf_counter()
             info = net.predict_h0(g, bt, h, f)
             t1 = time.perf_counter()
-            warm = ditr.solve(ctx, g, bt, h, f, warm=True, rel_tol=1e-9, allow=(ditr.OK,))
+            warm = ditr.solve(ctx, g, bt, h, f, warm=2, rel_tol=1e-9, allow=(ditr.OK,))
             torch.cuda.synchronize()
             tw, tp = time.perf_counter() - t0, t1 - t0
             if best_c is None or tc < best_c[0]:
@@ -284,14 +291,18 @@ def main():
     import ditgen
     from paper_1202_6168_amd import ditr
 
-    spec = ditgen.HEADLINE
+    spec = ditgen.LARGE if args.large else ditgen.HEADLINE
+    if args.n is not None or args.block is not None:
+        spec = ditgen.GraphSpec(n=args.n or spec.n, block=args.block or spec.block, seed=spec.seed)
     cp, ri = ditgen.generate(spec)
     b = ditgen.uniform_b(spec.n)
     dev = torch.device("cuda", 0)
     ctx = ditr.Context(0)
     t0 = time.perf_counter()
     cpt, rit = torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)
-    gopts = ditr.opts_default() if args.part_type is None else ditr.opts_default(part_type=args.part_type)
+    gopts = ditr.opts_default(part_nodes=args.part_nodes)
+    if args.part_type is not None:
+        gopts.part_type = args.part_type
     g = ditr.Graph(ctx, cpt, rit, opts=gopts)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t0)
@@ -301,6 +312,8 @@ def main():
     ft = torch.empty(spec.n, dtype=torch.float32, device=dev)
     opts = ditr.opts_default(mode=args.mode, flags=ditr.FLAG_TIME_KERNELS
                              | (ditr.FLAG_PRIORITY if args.priority else 0))
+    if args.alpha is not None:
+        opts.alpha = args.alpha
 
     for _ in range(args.warmup):
         ditr.solve(ctx, g, bt, ht, ft, rel_tol=args.tol, opts=opts, allow=(ditr.OK,))
@@ -345,9 +358,9 @@ def main():
         "dtype": "f32/f64",
         "data": "synthetic",
         "config": {
-            "workload": "D-iteration PageRank, synthetic web-like graph N=1e6, L=%d (block-1000 "
-                        "locality, Zipf out-degree, 10%% dangling), B=0.15/N, tol 1e-9 ||B||_1"
-                        % ri.size,
+            "workload": "D-iteration PageRank, synthetic web-like graph N=%.0e, L=%d (block-%d "
+                        "locality, Zipf out-degree, 10%% dangling), B=0.15/N, tol %g ||B||_1"
+                        % (spec.n, ri.size, spec.block, args.tol),
             "n": spec.n,
             "nnz": int(ri.size),
             "tol": args.tol,
@@ -355,8 +368,10 @@ def main():
             "partitions": K,
             "part_type": int(gopts.part_type),
             "priority_test": bool(args.priority),
+            "alpha": float(opts.alpha),
         },
         "edges_per_step": edges / args.steps,
+        "levels_per_step": sum(s.sweeps for s in stats) / args.steps,
         "normalized_iterations": edges / args.steps / ri.size,
         "final_resid_rel": last.resid_l1 / last.b_l1,
         "h_sum": float(h.sum()),
@@ -386,7 +401,7 @@ def main():
         out["batched"] = batched_bench(ctx, g, spec.n, dev)
     g.close()
     if not args.no_warm:
-        out["warm_start"] = warm_bench(ctx, dev)
+        out["warm_start"] = warm_bench(ctx, dev, args.warm_epochs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cp, ri, b, args.tol)
         # work efficiency: diffused edges per solve against the sequential FP64

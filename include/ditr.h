@@ -229,6 +229,11 @@ int ditr_residual(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, const d
  *   warm = 0: start from H = 0, F = B (d_h is overwritten).
  *   warm = 1: start from the H_0 held in d_h; F_0 = B + P H_0 - H_0
  *             (warm start and resume).
+ *   warm = 2: start from the H_0 in d_h and the F_0 in d_f that the caller
+ *             formed already (ditr_gnn_predict_h0 leaves both): one pass for
+ *             the norms instead of a residual; the first stage ends with the
+ *             exact residual of H, so the stop is certified even if the given
+ *             F_0 was inexact.
  * On return d_h = H and d_f = the exact residual of H rounded to FP32.
  * Synchronizes. Returns DITR_OK, DITR_NOT_CONVERGED, DITR_ABORTED or an error;
  * `stats` (may be NULL) is filled in every case. */
@@ -386,9 +391,11 @@ int ditr_gnn_train_step(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, const
  * ||B||_1 / N, H_0 = c xhat into d_h0 (device FP64 [n]) with c the first of
  * {0, 0.50, 0.55, ..., 1.50} that minimizes the L1 fluid ||B + c (P - I) xhat||_1
  * of the start (evaluated from the FP32 residual); d_f0 (device FP32 [n]) gets
- * the exact fluid B + P H_0 - H_0. c = 0 is the cold start H_0 = 0, F_0 = B
- * (info->fell_back = 1), so the start never holds more fluid than B. Then
- * ditr_solve(..., warm = 1, ...) diffuses from H_0. Synchronizes. */
+ * the start's fluid B + c (F - B), F = B + (P - I) xhat in FP64 rounded to FP32
+ * (equal to B + P H_0 - H_0 up to that rounding). c = 0 is the cold start
+ * H_0 = 0, F_0 = B (info->fell_back = 1), so the start never holds more fluid
+ * than B. Then ditr_solve(..., warm = 2, ...) diffuses from (H_0, F_0), or
+ * warm = 1 re-forms F_0 exactly. Synchronizes. */
 int ditr_gnn_predict_h0(ditr_ctx* ctx, ditr_gnn* net, const ditr_graph* g, const double* d_b,
                         double* d_h0, float* d_f0, ditr_gnn_start* info);
 

@@ -465,6 +465,7 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   };
   if (!c || !g || !d_b || !d_h || !d_f) return finish(set_error(DITR_EINVAL, "NULL argument"));
   if (!(rel_tol >= 0) || !std::isfinite(rel_tol)) return finish(set_error(DITR_EINVAL, "rel_tol must be >= 0"));
+  if (warm < 0 || warm > 2) return finish(set_error(DITR_EINVAL, "warm must be 0, 1 or 2"));
   ditr_opts o;
   ditr_opts_default(&o);
   if (opts) o = *opts;
@@ -486,6 +487,18 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     if (!rc) rc = read_ctrl(c);
     if (rc) return finish(rc);
     if (c->ctrl_host->err) return finish(set_error(DITR_ENONFINITE, "B holds NaN or Inf"));
+    b1 = c->ctrl_host->sum_abs;
+    r = c->ctrl_host->sum_abs_f32;
+    fmax = c->ctrl_host->max_abs;
+  } else if (warm == 2) {
+    // the caller's F holds B + P H_0 - H_0 already (rounded to FP32): one pass
+    // for ||B||_1, ||F_0||_1 and max |F_0|; the first exact refresh below
+    // replaces it, and the loop runs at least one stage so that the result is
+    // certified on an exact residual whatever the given F was
+    rc = launch_given_start(c, n, d_b, d_h, d_f);
+    if (!rc) rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    if (c->ctrl_host->err) return finish(set_error(DITR_ENONFINITE, "B, H_0 or F_0 holds NaN or Inf"));
     b1 = c->ctrl_host->sum_abs;
     r = c->ctrl_host->sum_abs_f32;
     fmax = c->ctrl_host->max_abs;
@@ -625,7 +638,9 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   int status = DITR_OK;
   double t_carry = 0;
   bool resident_ran = false;
-  while (r > target) {
+  bool must_refresh = warm == 2;  // a given F_0 is trusted for one stage only
+  while (r > target || must_refresh) {
+    must_refresh = false;
     if (st.rounds >= o.max_rounds) {
       status = DITR_NOT_CONVERGED;
       break;

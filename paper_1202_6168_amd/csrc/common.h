@@ -274,6 +274,7 @@ size_t pmass_temp_bytes(int64_t n, int64_t nnz);
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);
+int launch_given_start(ditr_ctx* c, int64_t n, const double* b, const double* h, const float* f);
 int launch_norm_f64(ditr_ctx* c, int64_t n, const double* x);
 int launch_refresh(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f);
 int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const double* h, float* f,

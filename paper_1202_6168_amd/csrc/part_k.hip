@@ -1407,6 +1407,19 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, 
   // error path runs with every wave leaving the kernel normally)
   int spin_limit = 1 << 24;
   if (const char* e = getenv("DITR_SPIN_LIMIT")) spin_limit = std::max(0, std::min(atoi(e), 1 << 24));
+  // DITR_PLAIN_LAUNCH=1 dispatches the same grid with an ordinary launch.
+  // part_resident_fits has checked that all K workgroups fit the device at
+  // once, so on an otherwise idle device they are all resident; if some were
+  // not, the bounded waits above end the launch with DITR_EHIP, never a hang.
+  // It exists for profiler runs: rocprofv3 crashes at process exit after a
+  // cooperative launch, once its results are written.
+  const char* pe = getenv("DITR_PLAIN_LAUNCH");
+  if (pe && atoi(pe) != 0) {
+    if (prio) k_part_resident<kPB, true><<<a.K, kPB, lds, c->stream>>>(a, spin_limit);
+    else k_part_resident<kPB, false><<<a.K, kPB, lds, c->stream>>>(a, spin_limit);
+    HIP_TRY(hipGetLastError());
+    return DITR_OK;
+  }
   void* args[] = {&a, &spin_limit};
   HIP_TRY(hipLaunchCooperativeKernel(prio ? reinterpret_cast<const void*>(&k_part_resident<kPB, true>)
                                           : reinterpret_cast<const void*>(&k_part_resident<kPB, false>),

@@ -106,6 +106,31 @@ __global__ void __launch_bounds__(kRedBlock) k_norm_f64(int64_t n, const double*
   }
 }
 
+// A start whose fluid is given: sums |B| (slot 0), max |F| (slot 1) and
+// |F| (slot 2) per block; err = 1 if B, H or F holds a NaN or Inf
+__global__ void __launch_bounds__(kRedBlock) k_given_start(int64_t n, const double* __restrict__ b,
+                                                           const double* __restrict__ h,
+                                                           const float* __restrict__ f, double* partials,
+                                                           int* err) {
+  double sb = 0, sf = 0, m = 0;
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * kRedBlock;
+  for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < n; i += stride) {
+    const double bv = b[i], hv = h[i], fv = (double)f[i];
+    bad |= !isfinite(bv) || !isfinite(hv) || !isfinite(fv);
+    sb += fabs(bv);
+    sf += fabs(fv);
+    m = fmax(m, fabs(fv));
+  }
+  if (bad) atomicOr(err, 1);
+  block_reduce3<kRedBlock>(sb, sf, m);
+  if (threadIdx.x == 0) {
+    partials[kPartialStride * blockIdx.x + 0] = sb;
+    partials[kPartialStride * blockIdx.x + 1] = m;
+    partials[kPartialStride * blockIdx.x + 2] = sf;
+  }
+}
+
 __global__ void __launch_bounds__(kRedBlock) k_check_finite(int64_t n, const double* __restrict__ x,
                                                              int* err) {
   bool bad = false;
@@ -643,6 +668,13 @@ int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f) {
 int launch_norm_f64(ditr_ctx* c, int64_t n, const double* x) {
   const int nb = grid_for(n, kRedBlock, (int)c->partials_cap);
   k_norm_f64<<<nb, kRedBlock, 0, c->stream>>>(n, x, c->partials, &c->ctrl->err);
+  HIP_TRY(hipGetLastError());
+  return finalize_partials(c, nb);
+}
+
+int launch_given_start(ditr_ctx* c, int64_t n, const double* b, const double* h, const float* f) {
+  const int nb = grid_for(n, kRedBlock, (int)c->partials_cap);
+  k_given_start<<<nb, kRedBlock, 0, c->stream>>>(n, b, h, f, c->partials, &c->ctrl->err);
   HIP_TRY(hipGetLastError());
   return finalize_partials(c, nb);
 }

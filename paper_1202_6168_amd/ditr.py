@@ -409,7 +409,9 @@ def solve(ctx: Context, g: Graph, b, h, f, warm: bool = False, rel_tol: float = 
             raise ValueError("b, h, f must be contiguous device vectors of length n")
     st = Stats()
     o = opts if opts is not None else opts_default()
-    rc = lib().ditr_solve(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f), int(bool(warm)),
+    if int(warm) not in (0, 1, 2):
+        raise ValueError("warm must be 0 (cold), 1 (H_0 given) or 2 (H_0 and its F_0 given)")
+    rc = lib().ditr_solve(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f), int(warm),
                           rel_tol, ctypes.byref(o), ctypes.byref(st))
     check(rc, allow)
     return st

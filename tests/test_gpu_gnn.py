@@ -188,8 +188,11 @@ def check_start(case, net, b):
     assert l1[k] <= l1.min() * (1 + 1e-5)
     assert np.allclose(H0, info.scale_c * xhat, rtol=1e-6, atol=0)
     exact = b + P @ H0 - H0
-    assert np.abs(F0 - exact).max() <= 2 ** -23 * np.abs(exact).max() + 1e-300
-    assert abs(info.f0_l1 - np.abs(exact).sum()) <= 1e-9 * b1
+    # F_0 = B + c (F - B) from F = B + (P - I) xhat rounded to FP32 (the
+    # identity is linear in H): exact up to that rounding and the final one
+    round_f = 2 ** -24 * (info.scale_c * np.abs(b + r) + np.abs(exact))
+    assert np.all(np.abs(F0 - exact) <= 2 * round_f + 1e-300)
+    assert abs(info.f0_l1 - np.abs(exact).sum()) <= 2 * round_f.sum() + 1e-15
     assert info.f0_l1 <= b1 * (1 + 1e-12)
     return info, l1
 
@@ -274,7 +277,7 @@ def test_learned_start_saves_diffusions(ctx):
         cold = ditr.solve(ctx, g, bt, h, f, rel_tol=1e-9, allow=(ditr.OK,))
         h_cold = h.cpu().numpy()
         info = net.predict_h0(g, bt, h, f)
-        warm = ditr.solve(ctx, g, bt, h, f, warm=True, rel_tol=1e-9, allow=(ditr.OK,))
+        warm = ditr.solve(ctx, g, bt, h, f, warm=2, rel_tol=1e-9, allow=(ditr.OK,))
         h_warm = h.cpu().numpy()
         print("graph %d: cold %.3e edges, warm %.3e edges (start fluid %.3f of B, c = %.2f)"
               % (s, cold.edges, warm.edges, info.f0_l1 / info.b_l1, info.scale_c))

@@ -425,3 +425,42 @@ def test_abort_keeps_identity(ctx, headline):
     ident = b + sparse_p(cp, ri) @ h - h
     assert np.abs(f - ident).sum() <= 1e-7 * np.abs(ident).sum() + 1e-14 * np.abs(h).sum()
     g.close()
+
+
+def test_warm_given_fluid_is_certified(ctx):
+    """warm = 2 takes the caller's F_0 for the first stage only: with the right
+    F_0 and with a wrong one (zeros), the result is certified on the exact
+    residual of its H and keeps parity with the oracle."""
+    cp, ri = ditgen.generate(ditgen.GraphSpec(n=30_000, block=1000, seed=12))
+    n = cp.size - 1
+    b = ditgen.uniform_b(n)
+    ref = oracle.solve(cp, ri, b, rel_tol=1e-13)
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, *upload(cp, ri))
+    bt = torch.from_numpy(b).to(dev)
+    h0 = ref.h * np.random.default_rng(3).uniform(0.7, 1.0, n)
+    for given in ("exact", "zeros"):
+        ht = torch.from_numpy(h0).to(dev)
+        ft = torch.empty(n, dtype=torch.float32, device=dev)
+        if given == "exact":
+            ditr.residual(ctx, g, bt, ht, ft)
+        else:
+            ft.zero_()
+        st = ditr.solve(ctx, g, bt, ht, ft, warm=2, rel_tol=1e-10, allow=(ditr.OK,))
+        torch.cuda.synchronize()
+        assert st.refreshes >= 1
+        check_parity(cp, ri, b, ht.cpu().numpy(), ft.cpu().numpy().astype(np.float64), st, 1e-10, ref=ref)
+    with pytest.raises(ValueError):
+        ditr.solve(ctx, g, bt, ht, ft, warm=3)
+    g.close()
+
+
+def test_plain_launch_parity(ctx, monkeypatch):
+    """DITR_PLAIN_LAUNCH dispatches the resident sweep with an ordinary launch
+    (for profiler runs); the result must keep parity like the cooperative one."""
+    monkeypatch.setenv("DITR_PLAIN_LAUNCH", "1")
+    cp, ri = ditgen.generate(ditgen.GraphSpec(n=50_000, block=1000, seed=13))
+    b = ditgen.uniform_b(cp.size - 1)
+    h, f, st = gpu_solve(ctx, cp, ri, b, 1e-10)
+    assert st.launches == st.rounds  # one resident launch per stage
+    check_parity(cp, ri, b, h, f, st, 1e-10)
