@@ -16,7 +16,7 @@
 //
 // Kernels: sparse aggregation P Z pulled over the transpose (heavy rows split
 // in 2048-link chunks), its adjoint P^T G gathered over the CSC columns, and
-// the dense layers on 16x16x16 BF16 MFMA tiles (forward, input gradient and
+// the dense layers on 16x16x32 BF16 MFMA tiles of gfx950 (forward, input gradient and
 // weight gradient), one wave per 16-node tile.
 #include <math.h>
 #include <string.h>
@@ -30,7 +30,7 @@
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));  // one MFMA operand of a lane
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kF0 = 16;   // padded feature width
@@ -199,12 +199,12 @@ __global__ void __launch_bounds__(256) k_agg_heavy_fin(int nh, const int32_t* __
 }
 
 // ---- dense layer: out = relu([Z | P Z] W + b) on MFMA tiles ---------------------
-// A wave computes 16 nodes x 64 outputs: (2 FIN / 16) k-steps x 4 output blocks
-// of v_mfma_f32_16x16x16_bf16. Operand layout (64 lanes, r = lane % 16,
-// q = lane / 16): A lane holds A[r][4q..4q+3], B lane holds B[4q..4q+3][r], the
-// result lane holds C[4q+i][r]. Wf is [64 out][2 FIN in] so a lane's B operand
-// is one 8-byte read. With HEAD the layer also writes z = out . w3 + b3 and
-// yhat = log(softplus(z)).
+// A wave computes 16 nodes x 64 outputs: (2 FIN / 32) k-steps x 4 output blocks
+// of v_mfma_f32_16x16x32_bf16 (gfx950). Operand layout (64 lanes, r = lane % 16,
+// q = lane / 16): A lane holds A[r][8q..8q+7], B lane holds B[8q..8q+7][r], the
+// result lane holds C[4q+i][r]. A lane's A operand is one 16-byte load of its
+// node's row; Wf is [64 out][2 FIN in] so its B operand is one 16-byte LDS read.
+// With HEAD the layer also writes z = out . w3 + b3 and yhat = log(softplus(z)).
 template <int FIN, bool HEAD>
 __global__ void __launch_bounds__(256) k_dense(int64_t n, const uint16_t* __restrict__ Z,
                                                const uint16_t* __restrict__ AZ,
@@ -233,17 +233,22 @@ __global__ void __launch_bounds__(256) k_dense(int64_t n, const uint16_t* __rest
     const int64_t node = tile * 16 + r;
     f32x4 acc[4];
     for (int nb = 0; nb < 4; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 av[K / 32];  // the tile's A operands, all loads issued first
 #pragma unroll
-    for (int ks = 0; ks < K / 16; ++ks) {
-      const int kb = ks * 16 + q * 4;
+    for (int ks = 0; ks < K / 32; ++ks) {
+      const int kb = ks * 32 + q * 8;
       const uint16_t* src = kb < FIN ? Z : AZ;
       const int col = kb < FIN ? kb : kb - FIN;
-      bf16x4 a = bf16x4{0, 0, 0, 0};
-      if (node < n) a = *reinterpret_cast<const bf16x4*>(src + node * FIN + col);
+      av[ks] = bf16x8{};
+      if (node < n) av[ks] = *reinterpret_cast<const bf16x8*>(src + node * FIN + col);
+    }
+#pragma unroll
+    for (int ks = 0; ks < K / 32; ++ks) {
+      const int kb = ks * 32 + q * 8;
 #pragma unroll
       for (int nb = 0; nb < 4; ++nb) {
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sW[(nb * 16 + r) * K + kb]);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sW[(nb * 16 + r) * K + kb]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], b, acc[nb], 0, 0, 0);
       }
     }
     float ys[4] = {0.f, 0.f, 0.f, 0.f};
@@ -330,7 +335,7 @@ __global__ void __launch_bounds__(256) k_head_bwd(int64_t n, const uint16_t* __r
 
 // ---- input gradient of layer 2: U = G2 [W2s | W2n]^T, [n][128] FP32 -------------
 // Wb is W2 in its natural [128 in][64 out] layout: a lane's B operand
-// B[k = out][n = in] = Wb[in][out .. out+3] is one 8-byte read.
+// B[k = out][n = in] = Wb[in][out .. out+7] is one 16-byte read (16x16x32 tiles).
 __global__ void __launch_bounds__(256) k_bwd_data(int64_t n, const uint16_t* __restrict__ G,
                                                   const uint16_t* __restrict__ Wb,
                                                   float* __restrict__ U) {
@@ -348,15 +353,19 @@ __global__ void __launch_bounds__(256) k_bwd_data(int64_t n, const uint16_t* __r
     const int64_t node = tile * 16 + r;
     f32x4 acc[8];
     for (int nb = 0; nb < 8; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 av[kHid / 32];
 #pragma unroll
-    for (int ks = 0; ks < kHid / 16; ++ks) {
-      const int kb = ks * 16 + q * 4;
-      bf16x4 a = bf16x4{0, 0, 0, 0};
-      if (node < n) a = *reinterpret_cast<const bf16x4*>(G + node * kHid + kb);
+    for (int ks = 0; ks < kHid / 32; ++ks) {
+      av[ks] = bf16x8{};
+      if (node < n) av[ks] = *reinterpret_cast<const bf16x8*>(G + node * kHid + ks * 32 + q * 8);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kHid / 32; ++ks) {
+      const int kb = ks * 32 + q * 8;
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sW[(nb * 16 + r) * kHid + kb]);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sW[(nb * 16 + r) * kHid + kb]);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], b, acc[nb], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -411,14 +420,15 @@ __global__ void __launch_bounds__(256) k_agg_t(int64_t n, const int32_t* __restr
 
 // ---- weight gradient: dW = [Z | P Z]^T G and db = sum G, per-block partials ------
 // The reduction runs over nodes, so both operands are staged transposed in LDS
-// ([feature][node], 64 nodes per step) and read as 8-byte MFMA operands.
+// ([feature][node], 64 nodes per step, rows padded to 72 entries so that every
+// 16-byte operand read is aligned) and read as 16x16x32 MFMA operands.
 // part[block] = [dW (2 FIN x 64, row-major [in][out]), db (64)]
 template <int FIN>
 __global__ void __launch_bounds__(256) k_bwd_w(int64_t n, const uint16_t* __restrict__ Z,
                                                const uint16_t* __restrict__ AZ,
                                                const uint16_t* __restrict__ G,
                                                float* __restrict__ part) {
-  constexpr int K = 2 * FIN, CH = 64, LD = CH + 4;
+  constexpr int K = 2 * FIN, CH = 64, LD = CH + 8;
   constexpr int TPW = (K / 16) * 4 / 4;  // 16x16 output tiles per wave
   __shared__ __attribute__((aligned(16))) uint16_t sZ[K * LD];
   __shared__ __attribute__((aligned(16))) uint16_t sG[kHid * LD];
@@ -454,14 +464,14 @@ __global__ void __launch_bounds__(256) k_bwd_w(int64_t n, const uint16_t* __rest
     }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < CH / 16; ++ks) {
-      const int kb = ks * 16 + q * 4;
+    for (int ks = 0; ks < CH / 32; ++ks) {
+      const int kb = ks * 32 + q * 8;
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         const int tile = wave * TPW + t, mb = tile / 4, nb = tile % 4;
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(&sZ[(mb * 16 + r) * LD + kb]);
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&sG[(nb * 16 + r) * LD + kb]);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sZ[(mb * 16 + r) * LD + kb]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sG[(nb * 16 + r) * LD + kb]);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
       }
     }
     if (threadIdx.x < kHid)
