@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--block", type=int, default=None, help="locality block of the generator")
     ap.add_argument("--part-nodes", type=int, default=0, help="nodes per partition (0: library)")
     ap.add_argument("--warm-epochs", type=int, default=40, help="training epochs of the warm start")
+    ap.add_argument("--weighted", action="store_true",
+                    help="a general matrix: the same graph with seeded signed weights, column l1 norm 0.85")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -303,7 +305,8 @@ def main():
     gopts = ditr.opts_default(part_nodes=args.part_nodes)
     if args.part_type is not None:
         gopts.part_type = args.part_type
-    g = ditr.Graph(ctx, cpt, rit, opts=gopts)
+    valt = torch.from_numpy(ditgen.signed_weights(cp)).to(dev) if args.weighted else None
+    g = ditr.Graph(ctx, cpt, rit, opts=gopts, val=valt)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t0)
     K = len(g.partitions()) - 1
@@ -335,6 +338,8 @@ def main():
     # rounds); the per-level relaunch path counts every launch
     resident = all(s.launches == s.rounds for s in stats)
     kernel = "k_part_resident" if resident else "k_part_sweep"
+    if args.mode == 2 or args.weighted:
+        kernel = "k_pull_sweep"
     # algorithmic bytes of a diffusion (no reuse on chip): per out-link 4 B index
     # + 8 B FP32 read-modify-write of the target's fluid; per diffused node 4 B
     # column pointer + 8 B fluid read and zero + 16 B FP64 history update
@@ -368,6 +373,7 @@ def main():
             "partitions": K,
             "part_type": int(gopts.part_type),
             "priority_test": bool(args.priority),
+            "matrix": "general, signed weights, column l1 norm 0.85" if args.weighted else "PageRank",
             "alpha": float(opts.alpha),
         },
         "edges_per_step": edges / args.steps,

@@ -175,3 +175,17 @@ def ppr_rhs_dense(n: int, seed_sets, mass: float = 0.15) -> np.ndarray:
     for r, s in enumerate(seed_sets):
         b[s, r] = mass / len(s)
     return b
+
+
+def signed_weights(col_ptr, c: float = 0.85, seed: int = 17) -> np.ndarray:
+    """One weight per CSC entry for a general matrix of the same graph: values
+    uniform in [-1, 1) with a seeded generator, each non-empty column scaled to
+    l1 norm c (so the matrix is contractive with factor c)."""
+    col_ptr = np.asarray(col_ptr, np.int64)
+    rng = np.random.default_rng(seed)
+    val = rng.uniform(-1.0, 1.0, int(col_ptr[-1]))
+    deg = np.diff(col_ptr)
+    col = np.repeat(np.arange(deg.size), deg)
+    norm = np.bincount(col, weights=np.abs(val), minlength=deg.size)
+    scale = np.where(norm > 0, c / np.where(norm > 0, norm, 1.0), 0.0)
+    return val * scale[col]
