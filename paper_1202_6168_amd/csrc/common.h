@@ -35,6 +35,7 @@ struct ditr_ctx {
   size_t lds_per_cu = 0;       // LDS of one CU
   size_t lds_dyn[3] = {0, 0, 0};  // dynamic LDS the persistent kernel may take (block 256/512/1024)
   size_t part_lds_dyn = 0;        // dynamic LDS the partitioned sweep may take
+  size_t part_lds_static = 0;     // largest static LDS of the partition kernels
   int* abort_host = nullptr;   // pinned, mapped
   int* abort_dev = nullptr;    // device view of abort_host
   Ctrl* ctrl = nullptr;        // device

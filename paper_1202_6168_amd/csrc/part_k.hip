@@ -546,8 +546,25 @@ __device__ void part_sweeps_t(const PartArgs& a, const PartView& v, double quant
       passed = 1;
       for (int e = e0; e < e1; e += 8) {
         int t[8];
+        if (TARGETS_LDS) {
+          // the eight 16-bit targets from five aligned words (three LDS reads
+          // instead of eight); the words past the last slot are padding
+          const int u = e + (v.lbase & 1);
+          const uint32_t* wp = v.lidx_words + (u >> 1);
+          const uint32_t sh = (uint32_t)(u & 1) * 16u;
+          uint32_t d[5];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) t[q] = lidx[min(e + q, e1 - 1)];  // in range, no per-slot branch
+          for (int k = 0; k < 5; ++k) d[k] = wp[k];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t win = __builtin_amdgcn_alignbit(d[k + 1], d[k], sh);
+            t[2 * k] = win & 0xFFFFu;
+            t[2 * k + 1] = win >> 16;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) t[q] = lidx[min(e + q, e1 - 1)];  // in range, no per-slot branch
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (e + q < e1) add_fixed(&v.Fq[t[q]], w);  // ds_add_u64
@@ -1259,7 +1276,7 @@ int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, d
 // LDS of a partition workgroup: 20 bytes per node (+4) and 2 bytes per local
 // target slot (two spare slots let the targets move as aligned 32-bit words)
 size_t part_lds_bytes(int nodes, int local_edges, bool prio) {
-  return (size_t)nodes * (prio ? 24 : 20) + 4 + (size_t)local_edges * 2 + 16;
+  return (size_t)nodes * (prio ? 24 : 20) + 4 + (size_t)local_edges * 2 + 32;
 }
 
 // dynamic LDS both partition kernels may take (the larger static part counts)
@@ -1267,7 +1284,11 @@ int part_configure(ditr_ctx* c) {
   const void* fns[] = {reinterpret_cast<const void*>(&k_part_sweep<kPB, false>),
                        reinterpret_cast<const void*>(&k_part_resident<kPB, false>),
                        reinterpret_cast<const void*>(&k_part_sweep<kPB, true>),
-                       reinterpret_cast<const void*>(&k_part_resident<kPB, true>)};
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, true>),
+                       reinterpret_cast<const void*>(&k_part_sweep<kPB / 2, false>),
+                       reinterpret_cast<const void*>(&k_part_sweep<kPB / 2, true>),
+                       reinterpret_cast<const void*>(&k_part_sweep<kPB / 4, false>),
+                       reinterpret_cast<const void*>(&k_part_sweep<kPB / 4, true>)};
   size_t stat = 0;
   for (const void* fn : fns) {
     hipFuncAttributes at;
@@ -1277,6 +1298,7 @@ int part_configure(ditr_ctx* c) {
     }
     stat = std::max(stat, at.sharedSizeBytes);
   }
+  c->part_lds_static = stat;
   for (size_t total : {c->lds_per_cu, c->lds_per_block}) {
     if (total <= stat + 64) continue;
     const size_t dyn = total - stat;
@@ -1353,13 +1375,28 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, fl
   int rc = part_args(c, g, sb, f, h, alpha, m, prio, &a, &lds);
   if (rc) return rc;
   const PartPlan& q = g->pp;
+  // Every workgroup loads its partition, sweeps it in LDS and publishes it, one
+  // after the other; a CU overlaps one workgroup's memory phases with another's
+  // LDS sweeps only when several fit. Smaller partitions therefore run in
+  // smaller workgroups: two of 512 threads per CU when the LDS of one fits in
+  // half the CU's, four of 256 in a quarter.
+  const size_t per_cu = c->lds_per_cu > c->part_lds_static ? c->lds_per_cu - c->part_lds_static : 0;
+  const int block = lds * 4 <= per_cu ? kPB / 4 : lds * 2 <= per_cu ? kPB / 2 : kPB;
   for (int s = 0; s < nlaunch; ++s) {
     const int64_t units = q.n_units;
     if (units > 0)
       k_part_items<<<(unsigned)std::min<int64_t>((units + 3) / 4, 16384), 256, 0, c->stream>>>(a, s & 1);
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s], c->stream));
-    if (prio) k_part_sweep<kPB, true><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
-    else k_part_sweep<kPB, false><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+    if (block == kPB) {
+      if (prio) k_part_sweep<kPB, true><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+      else k_part_sweep<kPB, false><<<a.K, kPB, lds, c->stream>>>(a, s & 1);
+    } else if (block == kPB / 2) {
+      if (prio) k_part_sweep<kPB / 2, true><<<a.K, kPB / 2, lds, c->stream>>>(a, s & 1);
+      else k_part_sweep<kPB / 2, false><<<a.K, kPB / 2, lds, c->stream>>>(a, s & 1);
+    } else {
+      if (prio) k_part_sweep<kPB / 4, true><<<a.K, kPB / 4, lds, c->stream>>>(a, s & 1);
+      else k_part_sweep<kPB / 4, false><<<a.K, kPB / 4, lds, c->stream>>>(a, s & 1);
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[2 * s + 1], c->stream));
   }
   HIP_TRY(hipGetLastError());

@@ -102,6 +102,14 @@ __global__ void __launch_bounds__(kPullBlock) k_pull_sweep(PullArgs a, int parit
     } else {
       int32_t e = r0;
       if (W) {
+        for (; e + 4 <= r1; e += 4) {  // four index and weight loads, then four gathers
+          const int32_t c0 = a.csr_col[e], c1 = a.csr_col[e + 1], c2 = a.csr_col[e + 2],
+                        c3 = a.csr_col[e + 3];
+          const double w0 = a.csr_val[e], w1 = a.csr_val[e + 1], w2 = a.csr_val[e + 2],
+                       w3 = a.csr_val[e + 3];
+          acc += w0 * (double)S_in[c0] + w1 * (double)S_in[c1] + w2 * (double)S_in[c2] +
+                 w3 * (double)S_in[c3];
+        }
         for (; e < r1; ++e) acc += a.csr_val[e] * (double)S_in[a.csr_col[e]];
       } else {
         for (; e + 4 <= r1; e += 4) {  // four index loads, then four gathers
