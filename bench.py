@@ -135,6 +135,41 @@ def cpu_baseline(cp, ri, b, tol):
     return out
 
 
+def trace_summary(ctx, g, bt, ht, ft, tol, opts, K, dev):
+    """One more solve, untimed, with the per-partition trace on (Section 2.4's
+    r_k and s_k per PID and level, Section 3.3's idle proportion): how the
+    level time splits into waiting for the other partitions and own work, and
+    how evenly the work and the fluid spread over the partitions."""
+    import numpy as np
+    import torch
+
+    from paper_1202_6168_amd import ditr
+
+    cap = 8192 * K
+    buf = torch.full((cap * ditr.TRACE_FIELDS,), float("nan"), dtype=torch.float64, device=dev)
+    ctx.set_trace(buf)
+    try:
+        st = ditr.solve(ctx, g, bt, ht, ft, rel_tol=tol, opts=opts, allow=(ditr.OK,))
+    finally:
+        ctx.set_trace(None)
+    torch.cuda.synchronize()
+    L = int(st.sweeps)
+    rec = buf[:min(L * K, cap) * ditr.TRACE_FIELDS].cpu().numpy().reshape(-1, K, ditr.TRACE_FIELDS)
+    held, sent, idle, busy = rec[..., 0], rec[..., 1], rec[..., 4], rec[..., 5]
+    level_s = (idle + busy).max(axis=1)  # a level ends with its slowest partition
+    return {
+        "levels": L,
+        "idle_share": float(idle.sum() / (idle + busy).sum()),
+        "busy_us_mean": float(1e6 * busy.mean()),
+        "busy_us_max_over_mean": float((busy.max(axis=1) / busy.mean(axis=1)).mean()),
+        "level_us_mean": float(1e6 * level_s.mean()),
+        "sent_share_mean": float((sent.sum(axis=1) / (held + sent).sum(axis=1)).mean()),
+        "fluid_decay_per_level": float(np.exp(np.mean(np.diff(np.log((held + sent).sum(axis=1)))))),
+        "idle_polls": int(st.idle_polls),
+        "note": "traced solve (a separate kernel instantiation), not part of the timed steps",
+    }
+
+
 def batched_bench(ctx, g, n, dev):
     """256 personalized right-hand sides in one batched solve vs plain solves."""
     import numpy as np
@@ -403,6 +438,8 @@ def main():
             "launches": klaunch,
         },
     }
+    if resident and args.mode in (0, 3) and not args.weighted:
+        out["trace"] = trace_summary(ctx, g, bt, ht, ft, args.tol, opts, K, dev)
     if not args.no_batched:
         out["batched"] = batched_bench(ctx, g, spec.n, dev)
     g.close()

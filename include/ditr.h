@@ -263,6 +263,33 @@ int ditr_solve_noalloc(ditr_ctx* ctx, const ditr_graph* g, const double* d_b, do
                        ditr_stats* stats);
 size_t ditr_noalloc_scratch_bytes(void);
 
+/* Per-partition trace of the partitioned sweep: the fluid r_k each partition
+ * (PID) still holds and the fluid s_k it has sent to the others but they have
+ * not yet taken in (the quantities of Section 2.4's PID model and of the fluid
+ * plots of Section 3.1), its work, and its idle time waiting for the others'
+ * exchange (the idle proportion of Section 3.3). Registers d_trace, a device
+ * buffer the caller owns and keeps alive while tracing is on, of `capacity`
+ * records of DITR_TRACE_FIELDS doubles each. NULL or capacity 0 switches
+ * tracing off (the default).
+ *
+ * Level l of a solve (counted over its stages; stats.sweeps is the number of
+ * levels) writes partition k's record at index l * K + k, if it is below
+ * `capacity`. Records past it are dropped. Fields, in order:
+ *   0 r_k: sum of |F_i| over the partition once the level's sweeps end;
+ *   1 s_k: the |shares| the level published for targets outside the partition
+ *          (received at the next level);
+ *   2 node diffusions of the level;
+ *   3 edge diffusions of the level;
+ *   4 seconds spent waiting for the other partitions before the level
+ *     (resident sweep; 0 when every level is its own launch);
+ *   5 seconds from the end of that wait to the partition's arrival (its work).
+ * For PageRank (nonnegative fluid), sum_k (r_k + s_k) at the last level of a
+ * stage equals the exact ||B + P H - H||_1 that follows it, up to the FP32 and
+ * fixed-point rounding of the moved fluid. Applies to DITR_MODE_PARTITION (and
+ * AUTO when it picks it); other modes write nothing. */
+#define DITR_TRACE_FIELDS 6
+int ditr_set_trace(ditr_ctx* ctx, double* d_trace, int64_t capacity);
+
 /* ---- batched personalized PageRank (step: many right-hand sides) -------- */
 /* Diffuse nrhs right-hand sides at once (multiple of 4, 4..256), each to its
  * own exact FP64 residual <= rel_tol * ||B_r||_1 (personalization vectors V of

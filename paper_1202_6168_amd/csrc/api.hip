@@ -92,6 +92,14 @@ int ditr_create(ditr_ctx** out, int device, void* hip_stream) {
     return set_error(DITR_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
   }
   c->num_cus = prop.multiProcessorCount;
+  {
+    int khz = 0;  // s_memrealtime runs at the device's wall-clock rate
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) {
+      (void)hipGetLastError();
+      khz = 100000;
+    }
+    c->tick_s = 1e-3 / (double)khz;
+  }
   c->lds_per_block = prop.sharedMemPerBlock;
   c->lds_per_cu = std::max<size_t>(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
   persistent_configure(c, c->lds_per_cu, c->lds_per_block);
@@ -138,6 +146,14 @@ int ditr_destroy(ditr_ctx* c) {
 int ditr_abort(ditr_ctx* c) {
   if (!c || !c->abort_host) return set_error(DITR_EINVAL, "ctx is NULL");
   __atomic_store_n(c->abort_host, 1, __ATOMIC_SEQ_CST);
+  return DITR_OK;
+}
+
+int ditr_set_trace(ditr_ctx* c, double* d_trace, int64_t capacity) {
+  if (!c) return set_error(DITR_EINVAL, "ctx is NULL");
+  if (capacity < 0) return set_error(DITR_EINVAL, "negative trace capacity");
+  c->trace = capacity > 0 ? d_trace : nullptr;
+  c->trace_cap = d_trace ? capacity : 0;
   return DITR_OK;
 }
 

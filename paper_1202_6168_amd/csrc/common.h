@@ -44,6 +44,9 @@ struct ditr_ctx {
   size_t partials_cap = 0;     // in blocks
   unsigned char* scratch = nullptr;  // this device's static scratch (ditr_solve_noalloc)
   size_t scratch_bytes = 0;
+  double* trace = nullptr;     // caller's per-partition trace (ditr_set_trace), or nullptr
+  int64_t trace_cap = 0;       // records of DITR_TRACE_FIELDS doubles
+  double tick_s = 0;           // seconds per tick of s_memrealtime
 };
 
 // Tables of the partitioned sweep (part_k.hip), built per partition plan.

@@ -190,7 +190,27 @@ struct PartArgs {
   float alpha;
   float d;
   double dd;  // damping in FP64 for the published shares
+  double* trace;      // per-partition trace records (nullptr: off), see ditr_set_trace
+  int64_t trace_cap;  // records
+  double tick_s;      // seconds per s_memrealtime tick
 };
+
+constexpr int kTrace = 6;  // doubles per trace record (DITR_TRACE_FIELDS)
+
+// thread 0 writes partition p's record of solve level `level` (if it fits)
+__device__ __forceinline__ void trace_write(const PartArgs& a, int64_t level, int p, double held, double sent,
+                                            double diffs, double edges, uint64_t idle_ticks,
+                                            uint64_t busy_ticks) {
+  const int64_t rec = level * a.K + p;
+  if (rec >= a.trace_cap) return;
+  double* t = a.trace + rec * kTrace;
+  t[0] = held;
+  t[1] = sent;
+  t[2] = diffs;
+  t[3] = edges;
+  t[4] = (double)idle_ticks * a.tick_s;
+  t[5] = (double)busy_ticks * a.tick_s;
+}
 
 // Fluid in LDS is fixed point: F = Fq q with q = T 2^-32 for the threshold T
 // of the level, so the test |F| > T is |Fq| > 2^32, a push is an integer LDS
@@ -233,6 +253,20 @@ __device__ __forceinline__ int block_or(int pred, int* slots) {
 #pragma unroll
   for (int w = 0; w < NW; ++w) any |= slots[w];
   return any;
+}
+
+// block-wide sum of one value, valid in thread 0 (its own LDS slots)
+template <int BLOCK>
+__device__ double block_sum_t0(double x) {
+  __shared__ double slot[BLOCK / 64];
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = x;
+  lds_barrier();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < BLOCK / 64; ++w) t += slot[w];
+  lds_barrier();  // slot is free again
+  return t;
 }
 
 // A partition's view of the dynamic LDS, indexed by local id (the partition's
@@ -583,12 +617,12 @@ __device__ void part_sweeps(const PartArgs& a, const PartView& v, double quantum
 
 // 4. H += dH and the shares p_i dH_i published for the outside targets, in node
 // order through inv (H, S and F move coalesced; eight nodes per thread in
-// flight). Sums |F| plus the fluid in flight to outside targets into resid and
-// the largest |F| into fmx. RESIDENT: F stays in LDS and dH restarts from zero;
-// otherwise F goes back to memory.
-template <int BLOCK, bool RESIDENT, bool PRIO>
+// flight). Sums |F| plus the fluid in flight to outside targets into resid, the
+// fluid in flight alone into sent, and the largest |F| into fmx. RESIDENT: F
+// stays in LDS and dH restarts from zero; otherwise F goes back to memory.
+template <int BLOCK, bool RESIDENT, bool PRIO, bool SENT = false>
 __device__ void part_publish(const PartArgs& a, const PartView& v, double quantum, float* S_out,
-                             double& resid, double& fmx) {
+                             double& resid, double& sent, double& fmx) {
   constexpr int U = 8;
   for (int j0 = threadIdx.x; j0 < v.np; j0 += U * BLOCK) {
     int r[U];
@@ -615,7 +649,9 @@ __device__ void part_publish(const PartArgs& a, const PartView& v, double quantu
         const int od = v.odeg[i];
         if (od > 0) {
           so = (float)(a.dd * dh / (double)od);
-          resid += fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
+          const double out = fabs((double)so) * (double)(od - (v.lptr[i + 1] - v.lptr[i]));
+          resid += out;
+          if (SENT) sent += out;
         }
       }
       if (RESIDENT) st_agent(&S_out[g], so);
@@ -683,17 +719,25 @@ __global__ void __launch_bounds__(BLOCK) k_part_sweep(PartArgs a, int parity) {
   const PartView v = part_view(a, smem, p);
 
   const double quantum = fixed_quantum(a.ctrl->T);
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+  const int64_t level = (int64_t)a.ctrl->sweeps;  // this launch's level of the solve
   part_load<BLOCK, PRIO>(a, v, 1.0 / quantum);
   part_inflow<BLOCK, false>(a, v, p, S_in, 1.0 / quantum, 0, 0);
   double edges = 0, diffs = 0;
   part_sweeps<BLOCK, PRIO>(a, v, quantum, edges, diffs, 0, a.m);
 
   // ---- 4. write back, publish p_i dH_i, partial sums
-  double resid = 0, fmx = 0;
-  part_publish<BLOCK, false, PRIO>(a, v, quantum, S_out, resid, fmx);
+  double resid = 0, sent = 0, fmx = 0;
+  part_publish<BLOCK, false, PRIO, true>(a, v, quantum, S_out, resid, sent, fmx);
 
   // ---- 5. per-workgroup sums; the last workgroup finishes the launch
   block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
+  if (a.trace) {
+    const double s_tot = block_sum_t0<BLOCK>(sent);
+    if (tid == 0)
+      trace_write(a, level, p, resid - s_tot, s_tot, diffs, edges, 0,
+                  __builtin_amdgcn_s_memrealtime() - t_start);
+  }
   if (tid == 0) {
     double* q = a.partials + (size_t)kStride * p;
     __hip_atomic_store(&q[0], resid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -745,8 +789,10 @@ __device__ __forceinline__ void wait_stores() {
 // arrival counter reaches `target`: thread 0 polls it at agent scope, the
 // workgroup meets on the result. A wait longer than spin_limit polls sets
 // ctrl->err = 2 and returns false; the caller then leaves the kernel, so every
-// wave exits even if some workgroup never arrives.
-__device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err, int* s_ok) {
+// wave exits even if some workgroup never arrives. The polls that found the
+// count short are added to *polls.
+__device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err, int* s_ok,
+                           unsigned long long* polls) {
   if (threadIdx.x == 0) {
     int ok = 1, spins = 0;
     while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -757,6 +803,7 @@ __device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err,
         break;
       }
     }
+    if (spins) __hip_atomic_fetch_add(polls, (unsigned long long)spins, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *s_ok = ok;
   }
   lds_barrier();
@@ -778,7 +825,9 @@ __device__ bool wait_count(const int* cnt, int target, int spin_limit, int* err,
 // level parity: a workgroup publishes level l only after every workgroup has
 // finished level l-1, so nobody still reads the level l-2 contents it
 // replaces. F goes back to memory when the stage ends.
-template <int BLOCK, bool PRIO>
+// TRACE: write the per-partition trace records (a separate instantiation, so
+// the untraced kernel carries none of its registers)
+template <int BLOCK, bool PRIO, bool TRACE>
 __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_limit) {
   const int tid = threadIdx.x;
   constexpr int NW = BLOCK / 64;
@@ -791,6 +840,10 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   int* err = &a.ctrl->err;
   const double target = a.ctrl->target;
   double T = a.ctrl->T;
+  // TRACE, thread 0: the solve's level count at the launch, the clock before
+  // and after the level's wait and at its arrival (in LDS, not in registers)
+  __shared__ long long s_tr[4];
+  if (TRACE && tid == 0) s_tr[0] = (long long)a.ctrl->sweeps;
   int done = 0, levels = 0, stop = 0;
   double edges_tail = 0, diffs_tail = 0;  // own counts of the last level, added at the end
 
@@ -813,8 +866,11 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     const int epoch = a.epoch0 + levels, ib = par * a.n_items;
     // everything of level l-1 is out (shares, sums); level 0 reads the zeroed
     // buffer of parity 1
-    if (levels > 0 && !wait_count(&arrive[par ^ 1], a.K * ((levels - 1) / 2 + 1), spin_limit, err, &s_ok))
+    if (TRACE && tid == 0) s_tr[1] = (long long)__builtin_amdgcn_s_memrealtime();
+    if (levels > 0 && !wait_count(&arrive[par ^ 1], a.K * ((levels - 1) / 2 + 1), spin_limit, err, &s_ok,
+                                  &a.ctrl->idle_polls))
       return;
+    if (TRACE && tid == 0) s_tr[2] = (long long)__builtin_amdgcn_s_memrealtime();
     // the outside shares are gathered first and land during the first local
     // sweep; they join the fluid before the second one
     float iv[8], lv[kLight];
@@ -857,8 +913,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     part_sweeps<BLOCK, PRIO>(a, v, quantum, edges, diffs, 1, a.m);
 
     // H += dH, publish p_i dH_i, partial sums (F stays in LDS)
-    double resid = 0, fmx = 0;
-    part_publish<BLOCK, true, PRIO>(a, v, quantum, S_out, resid, fmx);
+    double resid = 0, sent = 0, fmx = 0;
+    part_publish<BLOCK, true, PRIO>(a, v, quantum, S_out, resid, sent, fmx);
     double* part = a.partials + (size_t)par * a.K * kStride;
     block_reduce4<BLOCK>(resid, fmx, edges, diffs, red);
     edges_tail = edges;
@@ -874,9 +930,22 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     // every wave's shares, H and sums are out before the arrival
     wait_stores();
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&arrive[par], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) {
+      if (TRACE) s_tr[3] = (long long)__builtin_amdgcn_s_memrealtime();
+      __hip_atomic_fetch_add(&arrive[par], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (unit0 < a.n_units) unit_load(a, unit0, L0);  // for the next level, after the arrival
     light_prep(a, p, lsrc, lrow);
+    if (TRACE) {
+      // the fluid held, in a pass of its own after the arrival (the rest of
+      // resid is in flight); the record is written off the level's path
+      double held = 0;
+      for (int i = tid; i < v.np; i += BLOCK) held += fabs((double)v.Fq[i] * quantum);
+      held = block_sum_t0<BLOCK>(held);
+      if (tid == 0)
+        trace_write(a, s_tr[0] + levels, p, held, resid - held, diffs, edges, s_tr[2] - s_tr[1],
+                    s_tr[3] - s_tr[2]);
+    }
     if (stop) {
       ++levels;
       break;
@@ -1282,9 +1351,11 @@ size_t part_lds_bytes(int nodes, int local_edges, bool prio) {
 // dynamic LDS both partition kernels may take (the larger static part counts)
 int part_configure(ditr_ctx* c) {
   const void* fns[] = {reinterpret_cast<const void*>(&k_part_sweep<kPB, false>),
-                       reinterpret_cast<const void*>(&k_part_resident<kPB, false>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, false, false>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, false, true>),
                        reinterpret_cast<const void*>(&k_part_sweep<kPB, true>),
-                       reinterpret_cast<const void*>(&k_part_resident<kPB, true>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, true, false>),
+                       reinterpret_cast<const void*>(&k_part_resident<kPB, true, true>),
                        reinterpret_cast<const void*>(&k_part_sweep<kPB / 2, false>),
                        reinterpret_cast<const void*>(&k_part_sweep<kPB / 2, true>),
                        reinterpret_cast<const void*>(&k_part_sweep<kPB / 4, false>),
@@ -1356,6 +1427,9 @@ int part_args(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, d
   a.alpha = (float)alpha;
   a.d = (float)g->d;
   a.dd = g->d;
+  a.trace = c->trace;
+  a.trace_cap = c->trace ? c->trace_cap : 0;
+  a.tick_s = c->tick_s;
   if (part_lds_bytes(a.lds_nodes, 0, prio) > c->part_lds_dyn)
     return set_error(DITR_EINVAL, "partition of %d nodes needs %zu B of LDS (limit %zu)", a.lds_nodes,
                      part_lds_bytes(a.lds_nodes, 0, prio), c->part_lds_dyn);
@@ -1403,6 +1477,16 @@ int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, fl
   return DITR_OK;
 }
 
+namespace {
+// the resident sweep's instantiation for the node test and tracing
+const void* resident_fn(bool prio, bool trace) {
+  if (prio) return trace ? reinterpret_cast<const void*>(&k_part_resident<kPB, true, true>)
+                         : reinterpret_cast<const void*>(&k_part_resident<kPB, true, false>);
+  return trace ? reinterpret_cast<const void*>(&k_part_resident<kPB, false, true>)
+               : reinterpret_cast<const void*>(&k_part_resident<kPB, false, false>);
+}
+}  // namespace
+
 // Whether every partition workgroup of g can be resident at once (one
 // cooperative launch of K workgroups).
 int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits, bool prio) {
@@ -1412,8 +1496,8 @@ int part_resident_fits(ditr_ctx* c, const ditr_graph* g, bool* fits, bool prio) 
   int rc = part_args(c, g, graph_bufs(g), nullptr, nullptr, 1.5, 1, prio, &a, &lds);
   if (rc) return rc;
   int per_cu = 0;
-  const hipError_t oe = prio ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB, true>, kPB, lds)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_part_resident<kPB, false>, kPB, lds);
+  const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, resident_fn(prio, c->trace != nullptr), kPB, lds);
   if (oe != hipSuccess) {
     (void)hipGetLastError();
     return DITR_OK;
@@ -1450,17 +1534,13 @@ int launch_part_resident(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, 
   // not, the bounded waits above end the launch with DITR_EHIP, never a hang.
   // It exists for profiler runs: rocprofv3 crashes at process exit after a
   // cooperative launch, once its results are written.
+  const void* fn = resident_fn(prio, a.trace != nullptr);
+  void* args[] = {&a, &spin_limit};
   const char* pe = getenv("DITR_PLAIN_LAUNCH");
   if (pe && atoi(pe) != 0) {
-    if (prio) k_part_resident<kPB, true><<<a.K, kPB, lds, c->stream>>>(a, spin_limit);
-    else k_part_resident<kPB, false><<<a.K, kPB, lds, c->stream>>>(a, spin_limit);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipLaunchKernel(fn, dim3(a.K), dim3(kPB), args, lds, c->stream));
     return DITR_OK;
   }
-  void* args[] = {&a, &spin_limit};
-  HIP_TRY(hipLaunchCooperativeKernel(prio ? reinterpret_cast<const void*>(&k_part_resident<kPB, true>)
-                                          : reinterpret_cast<const void*>(&k_part_resident<kPB, false>),
-                                     dim3(a.K),
-                                     dim3(kPB), args, (unsigned)lds, c->stream));
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(a.K), dim3(kPB), args, (unsigned)lds, c->stream));
   return DITR_OK;
 }

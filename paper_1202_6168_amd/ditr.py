@@ -24,6 +24,7 @@ MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
 FLAG_NO_RESIDENT = 2
 FLAG_PRIORITY = 4
+TRACE_FIELDS = 6  # doubles per per-partition trace record (DITR_TRACE_FIELDS)
 GNN_PARAMS = 9409
 GNN_ACT_X, GNN_ACT_PX, GNN_ACT_H1, GNN_ACT_PH1, GNN_ACT_H2 = 0, 1, 2, 3, 4
 
@@ -136,6 +137,7 @@ _SIGNATURES = {
     "ditr_solve_noalloc": ([_vp, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.POINTER(Opts),
                             ctypes.POINTER(Stats)], _i32),
     "ditr_noalloc_scratch_bytes": ([], ctypes.c_size_t),
+    "ditr_set_trace": ([_vp, _vp, _i64], _i32),
     "ditr_solve_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, ctypes.POINTER(Opts),
                             _vp, ctypes.c_size_t, _vp, ctypes.POINTER(Stats)], _i32),
     "ditr_workspace_bytes": ([_vp, _i64, _i64, _i32, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)],
@@ -252,6 +254,20 @@ class Context:
 
     def abort(self):
         check(lib().ditr_abort(self.handle))
+
+    def set_trace(self, trace=None):
+        """Register a float64 CUDA tensor of TRACE_FIELDS * records elements as
+        the per-partition trace of the partitioned sweep (ditr_set_trace; the
+        tensor must stay alive while tracing is on), or switch it off (None).
+        Record l * K + k holds partition k at level l of a solve."""
+        if trace is None:
+            check(lib().ditr_set_trace(self.handle, None, 0))
+            self._trace = None
+            return
+        if trace.dtype != self.torch.float64 or not trace.is_cuda or not trace.is_contiguous():
+            raise ValueError("trace must be a contiguous float64 CUDA tensor")
+        check(lib().ditr_set_trace(self.handle, _ptr(trace), trace.numel() // TRACE_FIELDS))
+        self._trace = trace  # kept alive while registered
 
     def close(self):
         if self.handle:

@@ -1,0 +1,117 @@
+"""Per-partition trace of the partitioned sweep (ditr_set_trace): the fluid r_k
+a partition holds, the fluid s_k it has published for other partitions
+(Section 2.4's PID quantities, the fluid plots of Section 3.1), its work, and
+its wait for the others (the idle proportion of Section 3.3).
+
+Checks that do not depend on timing:
+  * every level of the solve (stats.sweeps of them) writes one record per
+    partition, and nothing is written past the registered capacity;
+  * the recorded diffusions and edges add up to the solve's counts;
+  * for PageRank the fluid is nonnegative, so the exact residual that follows
+    the last level is that level's held plus in-flight fluid:
+    ||B + P H - H||_1 = sum_k (r_k + s_k), up to the rounding of the fluid
+    moved in the last stage (which starts from an exact refresh).
+"""
+import numpy as np
+import pytest
+
+import ditgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1202_6168_amd import ditr  # noqa: E402
+
+F = ditr.TRACE_FIELDS
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = ditr.Context(0)
+    yield c
+    c.set_trace(None)
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def problem():
+    cp, ri = ditgen.generate(ditgen.GraphSpec(n=30_000, block=100, seed=4))
+    return cp, ri, ditgen.uniform_b(cp.size - 1)
+
+
+def run(ctx, problem, flags, capacity, guard=16, part_nodes=1000, tol=1e-9):
+    cp, ri, b = problem
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev),
+                   opts=ditr.opts_default(part_nodes=part_nodes))
+    K = len(g.partitions()) - 1
+    buf = torch.full((capacity * F + guard,), float("nan"), dtype=torch.float64, device=dev)
+    ctx.set_trace(buf[:capacity * F])  # the guard after it is not registered
+    bt = torch.from_numpy(b).to(dev)
+    ht = torch.empty(b.size, dtype=torch.float64, device=dev)
+    ft = torch.empty(b.size, dtype=torch.float32, device=dev)
+    try:
+        st = ditr.solve(ctx, g, bt, ht, ft, rel_tol=tol,
+                        opts=ditr.opts_default(mode=ditr.MODE_PARTITION, flags=flags))
+    finally:
+        ctx.set_trace(None)
+    torch.cuda.synchronize()
+    g.close()
+    out = buf.cpu().numpy()
+    return K, st, out[:capacity * F].reshape(capacity, F), out[capacity * F:], np.abs(b).sum()
+
+
+@pytest.mark.parametrize("flags", [0, ditr.FLAG_NO_RESIDENT], ids=["resident", "relaunch"])
+def test_trace_accounts_for_the_solve(ctx, problem, flags):
+    cap = 4096 * 64
+    K, st, rec, guard, b1 = run(ctx, problem, flags, cap)
+    assert st.status == ditr.OK
+    L = int(st.sweeps)
+    assert 2 <= L and L * K <= cap
+    written = rec[:L * K]
+    assert np.isfinite(written).all(), "a level left a partition's record unwritten"
+    assert np.isnan(rec[L * K:]).all(), "records written past the solve's levels"
+    assert np.isnan(guard).all()
+    assert (written >= 0).all()
+    # the counts add up to the solve's
+    assert written[:, 2].sum() == st.diffusions
+    assert written[:, 3].sum() == st.edges
+    # work is timed; a relaunched level has no wait
+    assert (written[:, 5] > 0).any()
+    if flags & ditr.FLAG_NO_RESIDENT:
+        assert (written[:, 4] == 0).all()
+    else:
+        assert st.idle_polls >= 0
+    # nonnegative fluid: the exact residual after the last level is its held
+    # plus in-flight fluid (up to the rounding of the last stage's moved fluid)
+    last = written[(L - 1) * K:L * K]
+    tracked = last[:, 0].sum() + last[:, 1].sum()
+    assert abs(tracked - st.resid_l1) <= 1e-4 * st.resid_l1 + 1e-13 * b1, (tracked, st.resid_l1)
+
+
+def test_trace_capacity_is_respected(ctx, problem):
+    cap = 40  # fewer records than one solve writes
+    K, st, rec, guard, _ = run(ctx, problem, 0, cap)
+    assert st.status == ditr.OK and st.sweeps * K > cap
+    assert np.isfinite(rec).all()
+    assert np.isnan(guard).all(), "a record was written past the capacity"
+
+
+def test_trace_off_writes_nothing(ctx, problem):
+    cp, ri, b = problem
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev),
+                   opts=ditr.opts_default(part_nodes=1000))
+    buf = torch.full((1024 * F,), float("nan"), dtype=torch.float64, device=dev)
+    ctx.set_trace(buf)
+    ctx.set_trace(None)
+    bt = torch.from_numpy(b).to(dev)
+    ht = torch.empty(b.size, dtype=torch.float64, device=dev)
+    ft = torch.empty(b.size, dtype=torch.float32, device=dev)
+    st = ditr.solve(ctx, g, bt, ht, ft, rel_tol=1e-9)
+    torch.cuda.synchronize()
+    g.close()
+    assert st.status == ditr.OK
+    assert np.isnan(buf.cpu().numpy()).all()
