@@ -53,7 +53,10 @@ size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part
   const size_t tiles = N / 4096 + 2;
   const size_t nh = std::min<size_t>(N, L / (kHeavyRow + 1) + 1);
   const size_t nc = L / kHeavyChunk + nh + 1;
-  const size_t ni = L / 5 + 1;
+  // a heavy row has more than kPartHeavy external in-links, and an item at
+  // most kItem of them
+  const size_t nhp = std::min<size_t>(N, L / (kPartHeavy + 1) + 1);
+  const size_t ni = nhp + L / kItem + 1;
   const size_t nu = (L / 4 + ni) / 64 + 9;
   size_t b = 0;
   // graph tables and the transpose
@@ -65,11 +68,14 @@ size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part
   // one partition plan (each retry reuses the same space)
   b += al(4 * (K + 1)) + al(8 * K) + al(4 * K) + al(8 * (K + 1));
   if (part_type == DITR_PART_PMASS) b += pmass_temp_bytes(n, nnz);
-  // the partitioned-sweep tables
-  b += al(4 * N) + 5 * al(4 * (N + 1)) + 3 * al(4 * tiles);
+  // the partitioned-sweep tables and the temporaries of their build (left in
+  // place in a workspace): ids, local CSC, external links, heavy rows, items
+  // and their work units, the two sorts, six scans
+  b += al(4 * N) + al(2 * N) + 6 * al(4 * (N + 1)) + 2 * al(8 * N) + 2 * al(4 * N) +
+       al(plan_sort_temp_bytes(n, (int64_t)ni)) + 6 * al(4 * tiles) + al(4) + 2 * al(4 * (N + 1));
   b += al(2 * (L + 4)) + al(4 * L) + al(2 * L) + al(4 * L);
-  b += al(4 * (K + 1)) + al(4 * N) + al(4 * ni) + al(4 * (K + 1)) + al(2048 * nu) + al(256 * nu) +
-       al(16 * ni) + al(4 * (K + 1)) + al(4 * N) + al(4 * N) + al(8 * N) + al(32) + al(128 * K) +
-       al(4 * (K + 1)) + al(2 * N);
+  b += 3 * al(4 * (K + 1)) + al(4 * nhp) + 2 * al(4 * (nhp + 1));
+  b += al(4 * ni) + 6 * al(4 * ni) + 2 * al(4 * (ni + 1)) + al(2048 * nu) + al(256 * nu) + al(16 * ni);
+  b += al(4 * N) + al(8 * N) + al(32) + al(128 * K);
   return b + 64 * kAlign;
 }

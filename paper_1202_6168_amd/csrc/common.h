@@ -58,7 +58,6 @@ struct PartPlan {
   uint16_t* inv = nullptr;       // [n] local id of each node: its rank in the partition's
                                  //   visiting order (falling local out-degree)
   float* pw = nullptr;           // [n] d / #out_i (0 for a dangling node)
-  int32_t* ext_deg = nullptr;    // [n] out-links leaving the partition
   int32_t* ext_ptr = nullptr;    // [K+1] external in-links of each partition (light rows)
   int32_t* ext_src = nullptr;    //   source node
   uint16_t* ext_row = nullptr;   //   target - partition start
@@ -131,6 +130,7 @@ struct ditr_graph {
 constexpr int kHeavyRow = 64;     // in-degree above which a row's in-links are split in chunks
 constexpr int kHeavyChunk = 2048; // in-links per chunk workgroup
 constexpr int kPartHeavy = 4;     // external in-links above which a row's inflow is summed in items
+constexpr int kItem = 512;        // links of a heavy row summed by one wave (8 per lane)
 // lowest threshold of the partitioned sweep relative to the total fluid (its
 // LDS fluid is fixed point in units of T 2^-32)
 constexpr double kPartTFloor = 1.0 / 268435456.0;  // 2^-28
@@ -295,6 +295,7 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g);
 void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges, bool prio = false);
+size_t plan_sort_temp_bytes(int64_t n, int64_t ni);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
                         double target, double T0);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,

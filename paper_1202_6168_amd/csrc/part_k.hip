@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.h"
 
 namespace {
@@ -29,7 +31,6 @@ namespace {
 constexpr int kPB = 1024;     // threads per partition workgroup
 constexpr int kStride = 8;    // doubles per block in the partials (sums, abort vote)
 constexpr int kCounters = 8;  // launch finish count, level arrivals of the resident sweep
-constexpr int kItem = 512;    // links of a heavy row summed by one wave (8 per lane)
 
 int grid_for(int64_t n, int block, int cap) {
   int64_t g = (n + block - 1) / block;
@@ -55,19 +56,51 @@ __global__ void k_count_local(int64_t n, const int32_t* __restrict__ col_ptr,
   }
 }
 
+// sort keys of the visiting order: partition, then falling local out-degree
+__global__ void k_order_keys(int64_t n, const int32_t* __restrict__ pid, const int32_t* __restrict__ cnt,
+                             unsigned long long* key, int32_t* val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    key[i] = ((unsigned long long)(uint32_t)pid[i] << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)cnt[i]);
+    val[i] = (int32_t)i;
+  }
+}
+
+// from the sorted order: each node's local id, and the local out-degrees in
+// visiting order (partitions are contiguous ranges, so position j of the sort
+// lies in the partition of the node it holds)
+__global__ void k_inv(int64_t n, const int32_t* __restrict__ ord, const int32_t* __restrict__ pid,
+                      const int32_t* __restrict__ part_ptr, const int32_t* __restrict__ cnt, uint16_t* inv,
+                      int32_t* degp) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
+    const int32_t i = ord[j];
+    inv[i] = (uint16_t)(j - part_ptr[pid[i]]);
+    degp[j] = cnt[i];
+  }
+}
+
+// local targets of node i, as local ids, at the position of i's local id
 __global__ void k_fill_local(int64_t n, const int32_t* __restrict__ col_ptr,
                              const int32_t* __restrict__ row_idx, const int32_t* __restrict__ pid,
-                             const int32_t* __restrict__ part_ptr,
+                             const int32_t* __restrict__ part_ptr, const uint16_t* __restrict__ inv,
                              const int32_t* __restrict__ loc_ptr, uint16_t* loc_idx) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int32_t pi = pid[i], lo = part_ptr[pi];
-    int32_t w = loc_ptr[i];
+    const int32_t pi = pid[i];
+    int32_t w = loc_ptr[part_ptr[pi] + inv[i]];
     for (int32_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) {
       const int32_t j = row_idx[e];
-      if (pid[j] == pi) loc_idx[w++] = (uint16_t)(j - lo);
+      if (pid[j] == pi) loc_idx[w++] = inv[j];
     }
   }
+}
+
+// largest number of local targets of one partition
+__global__ void k_part_max_edges(int K, const int32_t* __restrict__ part_ptr, const int32_t* __restrict__ loc_ptr,
+                                 int32_t* mx) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x)
+    atomicMax(mx, loc_ptr[part_ptr[k + 1]] - loc_ptr[part_ptr[k]]);
 }
 
 // per row: external in-links, split into light (partition stream) and heavy
@@ -94,7 +127,7 @@ __global__ void k_count_ext(int64_t n, const int32_t* __restrict__ row_ptr,
 
 __global__ void k_fill_ext(int64_t n, const int32_t* __restrict__ row_ptr,
                            const int32_t* __restrict__ csr_col, const int32_t* __restrict__ pid,
-                           const int32_t* __restrict__ part_ptr,
+                           const uint16_t* __restrict__ inv,
                            const int32_t* __restrict__ light_ptr, const int32_t* __restrict__ heavy_ptr,
                            int32_t* ext_src, uint16_t* ext_row, int32_t* heavy_src) {
   const int lane = threadIdx.x & 63;
@@ -104,7 +137,7 @@ __global__ void k_fill_ext(int64_t n, const int32_t* __restrict__ row_ptr,
     const int32_t pj = pid[j];
     const bool heavy = heavy_ptr[j + 1] > heavy_ptr[j];
     int32_t w = heavy ? heavy_ptr[j] : light_ptr[j];
-    const uint16_t jl = (uint16_t)(j - part_ptr[pj]);
+    const uint16_t jl = inv[j];  // the row's local id
     const int32_t r1 = row_ptr[j + 1];
     for (int32_t e0 = row_ptr[j]; e0 < r1; e0 += 64) {  // wave-wide, in CSR order
       const int32_t e = e0 + lane;
@@ -134,20 +167,101 @@ __global__ void k_gather_ptr(int K, const int32_t* __restrict__ part_ptr,
     out[k] = row_scan[part_ptr[k]];
 }
 
-__global__ void k_heavy_list(int64_t n, const int32_t* __restrict__ heavy_ptr, int32_t* list,
-                             int* count) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride)
-    if (heavy_ptr[j + 1] > heavy_ptr[j]) list[atomicAdd(count, 1)] = (int32_t)j;
+// out[k] = idx[ptr[k]]: the start of partition k's range in a list indexed by
+// a position of ptr
+__global__ void k_gather_ptr2(int K, const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                              int32_t* out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= K; k += gridDim.x * blockDim.x) out[k] = idx[ptr[k]];
 }
 
-__global__ void k_weights(int64_t n, const int32_t* __restrict__ col_ptr,
-                          const int32_t* __restrict__ loc_ptr, float d, float* pw, int32_t* ext_deg) {
+__global__ void k_heavy_flag(int64_t n, const int32_t* __restrict__ heavy_ptr, int32_t* flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride)
+    flag[j] = heavy_ptr[j + 1] > heavy_ptr[j];
+}
+
+__global__ void k_heavy_rows(int64_t n, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                             int32_t* rows) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride)
+    if (flag[j]) rows[pos[j]] = (int32_t)j;
+}
+
+// items of kItem links per heavy row
+__global__ void k_item_count(int32_t nh, const int32_t* __restrict__ rows, const int32_t* __restrict__ heavy_ptr,
+                             int32_t* cnt) {
+  for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+    const int32_t r = rows[h];
+    cnt[h] = (heavy_ptr[r + 1] - heavy_ptr[r] + kItem - 1) / kItem;
+  }
+}
+
+// lanes of an item's group: 2^l, the fewest whose eight slots hold its links
+__device__ __forceinline__ int item_lg2(int32_t links) {
+  int l = 0;
+  while ((8 << l) < links) ++l;
+  return l;
+}
+
+// every item: its row (local id), link range, and its size class (6 - log2 of
+// its lanes, so an ascending sort puts the largest groups first)
+__global__ void k_item_fill(int32_t nh, const int32_t* __restrict__ rows, const int32_t* __restrict__ heavy_ptr,
+                            const int32_t* __restrict__ ioff, const uint16_t* __restrict__ inv, int32_t* item_row,
+                            int32_t* ibeg, int32_t* iend, uint32_t* ikey, int32_t* ival) {
+  for (int32_t h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+    const int32_t r = rows[h], b0 = heavy_ptr[r], b1 = heavy_ptr[r + 1];
+    int32_t idx = ioff[h];
+    for (int32_t b = b0; b < b1; b += kItem, ++idx) {
+      const int32_t e = min(b + kItem, b1);
+      item_row[idx] = inv[r];
+      ibeg[idx] = b;
+      iend[idx] = e;
+      ikey[idx] = (uint32_t)(6 - item_lg2(e - b));
+      ival[idx] = idx;
+    }
+  }
+}
+
+__global__ void k_unit_lanes(int32_t ni, const int32_t* __restrict__ by, const int32_t* __restrict__ ibeg,
+                             const int32_t* __restrict__ iend, int32_t* gl) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < ni; j += gridDim.x * blockDim.x) {
+    const int32_t k = by[j];
+    gl[j] = 1 << item_lg2(iend[k] - ibeg[k]);
+  }
+}
+
+// sorted item j (item by[j]) takes lanes loff[j] .. loff[j] + gl of the unit
+// table: lane l of its group sums slots l, l + gl, ..., l + 7 gl of its links;
+// the leader's meta word names the item
+__global__ void k_unit_fill(int32_t ni, const int32_t* __restrict__ by, const int32_t* __restrict__ loff,
+                            const int32_t* __restrict__ ibeg, const int32_t* __restrict__ iend,
+                            const int32_t* __restrict__ hsrc, int32_t* usrc, int32_t* umeta) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < ni; j += gridDim.x * blockDim.x) {
+    const int32_t k = by[j], L = loff[j];
+    const int32_t gl = loff[j + 1] - L;
+    const int lg = __builtin_ctz((unsigned)gl);
+    const int64_t u = L >> 6;
+    const int lane = L & 63;
+    for (int l = 0; l < gl; ++l) {
+      umeta[u * 64 + lane + l] = ((l == 0 ? k + 1 : 0) << 3) | lg;
+      for (int qq = 0; qq < 8; ++qq) {
+        const int32_t e = ibeg[k] + l + gl * qq;
+        usrc[u * 512 + (int64_t)qq * 64 + lane + l] = e < iend[k] ? hsrc[e] : -1;
+      }
+    }
+  }
+}
+
+__global__ void k_fill_i32p(int32_t* p, int64_t n, int32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_weights(int64_t n, const int32_t* __restrict__ col_ptr, float d, float* pw) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
     const int32_t k = col_ptr[i + 1] - col_ptr[i];
     pw[i] = k > 0 ? d / (float)k : 0.f;  // p_ji for every out-link of i
-    ext_deg[i] = k - (loc_ptr[i + 1] - loc_ptr[i]);
   }
 }
 
@@ -161,8 +275,6 @@ struct PartArgs {
   const int32_t* __restrict__ loc_ptr;
   const uint16_t* __restrict__ loc_idx;
   const uint16_t* __restrict__ inv;    // [n] local id of each node in its partition
-  const float* __restrict__ pw;
-  const int32_t* __restrict__ ext_deg;
   const int32_t* __restrict__ ext_ptr;   // [K+1] light external in-links of each partition
   const int32_t* __restrict__ ext_src;
   const uint16_t* __restrict__ ext_row;
@@ -993,7 +1105,7 @@ __global__ void k_gather_ranges(int32_t nh, const int32_t* __restrict__ rows,
 
 void free_part_plan(ditr_graph* g) {
   PartPlan& q = g->pp;
-  for (void* p : {(void*)q.pid, (void*)q.loc_ptr, (void*)q.loc_idx, (void*)q.pw, (void*)q.ext_deg,
+  for (void* p : {(void*)q.pid, (void*)q.loc_ptr, (void*)q.loc_idx, (void*)q.pw,
                   (void*)q.ext_ptr, (void*)q.ext_src, (void*)q.ext_row, (void*)q.heavy_rows,
                   (void*)q.part_heavy, (void*)q.heavy_src, (void*)q.item_row, (void*)q.part_items,
                   (void*)q.unit_src, (void*)q.unit_meta, (void*)q.item_word,
@@ -1002,20 +1114,30 @@ void free_part_plan(ditr_graph* g) {
   q = PartPlan();
 }
 
-// Build the partitioned-sweep tables for the current partition plan of g.
+// device temporary bytes of the plan build's two radix sorts (n nodes, ni items)
+size_t plan_sort_temp_bytes(int64_t n, int64_t ni) {
+  size_t a = 0, b = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                           (int32_t*)nullptr, (int32_t*)nullptr, (int)std::max<int64_t>(n, 1), 0,
+                                           64, nullptr);
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint32_t*)nullptr, (uint32_t*)nullptr, (int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)std::max<int64_t>(ni, 1), 0, 3, nullptr);
+  return a + b;
+}
+
+// Build the partitioned-sweep tables for the current partition plan of g, all
+// on the device (sorts and scans; the host reads back only sizes).
 int build_part_plan(ditr_ctx* c, ditr_graph* g) {
   free_part_plan(g);
   PartPlan& q = g->pp;
   const int64_t n = g->n;
   const int K = (int)g->K;
   hipStream_t st = c->stream;
-  int32_t *cnt = nullptr, *cnt2 = nullptr, *light_ptr = nullptr, *heavy_ptr = nullptr;
+  std::vector<void*> temps;  // freed (or left in the workspace) at the end
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(st);
-    g_free(g, cnt);
-    g_free(g, cnt2);
-    g_free(g, light_ptr);
-    g_free(g, heavy_ptr);
+    for (void* p : temps) g_free(g, p);
+    temps.clear();
   };
 #define PP_TRY(expr)                                                                     \
   do {                                                                                   \
@@ -1025,234 +1147,189 @@ int build_part_plan(ditr_ctx* c, ditr_graph* g) {
       return set_error(DITR_EHIP, "%s failed: %s", #expr, hipGetErrorString(_e));        \
     }                                                                                    \
   } while (0)
+#define PP_RC(expr)            \
+  do {                         \
+    const int _rc = (expr);    \
+    if (_rc) {                 \
+      cleanup();               \
+      return _rc;              \
+    }                          \
+  } while (0)
+  auto temp = [&](void** p, size_t bytes) -> hipError_t {
+    const hipError_t e = g_alloc(g, p, bytes);
+    if (e == hipSuccess) temps.push_back(*p);
+    return e;
+  };
+  auto read_i32 = [&](const int32_t* d, int32_t* h) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+  };
   if (g->max_part > 65536) return set_error(DITR_EINVAL, "partitions above 65536 nodes");
-  PP_TRY(g_alloc(g, (void**)&q.pid, sizeof(int32_t) * n));
-  PP_TRY(g_alloc(g, (void**)&q.loc_ptr, sizeof(int32_t) * (n + 1)));
-  PP_TRY(g_alloc(g, (void**)&cnt, sizeof(int32_t) * (n + 1)));
-  PP_TRY(g_alloc(g, (void**)&cnt2, sizeof(int32_t) * (n + 1)));
-  PP_TRY(g_alloc(g, (void**)&light_ptr, sizeof(int32_t) * (n + 1)));
-  PP_TRY(g_alloc(g, (void**)&heavy_ptr, sizeof(int32_t) * (n + 1)));
   const int gb = grid_for(n, 256, 8192);
   const int gw = grid_for(n * 64, 256, 16384);  // one wave per row
+  int32_t *cnt, *cnt2, *light_ptr, *heavy_ptr, *ord_in, *ord, *degp;
+  unsigned long long *key_in, *key_out;
+  PP_TRY(g_alloc(g, (void**)&q.pid, sizeof(int32_t) * n));
+  PP_TRY(g_alloc(g, (void**)&q.inv, sizeof(uint16_t) * std::max<int64_t>(1, n)));
+  PP_TRY(g_alloc(g, (void**)&q.loc_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&cnt, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&cnt2, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&light_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&heavy_ptr, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&degp, sizeof(int32_t) * (n + 1)));
   k_fill_pid<<<std::min(K, 8192), 256, 0, st>>>(K, g->part_ptr, q.pid);
   k_count_local<<<gb, 256, 0, st>>>(n, g->col_ptr, g->row_idx, q.pid, cnt);
   PP_TRY(hipGetLastError());
-  int rc = scan_exclusive_i32(c, cnt, n, q.loc_ptr, g);
-  if (rc) { cleanup(); return rc; }
+
+  // visiting order of each partition's nodes: falling local out-degree, ties in
+  // node order (a stable radix sort of (partition, ~degree)), so that the 64
+  // lanes of a wave push lists of about the same length; local id r of
+  // partition k is node ord[lo_k + r], and inv maps a node to its local id
+  {
+    PP_TRY(temp((void**)&key_in, sizeof(unsigned long long) * std::max<int64_t>(1, n)));
+    PP_TRY(temp((void**)&key_out, sizeof(unsigned long long) * std::max<int64_t>(1, n)));
+    PP_TRY(temp((void**)&ord_in, sizeof(int32_t) * std::max<int64_t>(1, n)));
+    PP_TRY(temp((void**)&ord, sizeof(int32_t) * std::max<int64_t>(1, n)));
+    k_order_keys<<<gb, 256, 0, st>>>(n, q.pid, cnt, key_in, ord_in);
+    int kbits = 1;
+    while (kbits < 31 && (1LL << kbits) < (int64_t)K) ++kbits;
+    size_t tb = 0;
+    PP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key_in, key_out, ord_in, ord, (int)n, 0, 32 + kbits, st));
+    void* tmp = nullptr;
+    PP_TRY(temp(&tmp, tb));
+    PP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key_in, key_out, ord_in, ord, (int)n, 0, 32 + kbits, st));
+    k_inv<<<gb, 256, 0, st>>>(n, ord, q.pid, g->part_ptr, cnt, q.inv, degp);
+    PP_TRY(hipGetLastError());
+  }
+  // local CSC in visiting order (pointer by local id, targets as local ids)
+  PP_RC(scan_exclusive_i32(c, degp, n, q.loc_ptr, g));
   int32_t nloc = 0;
-  PP_TRY(hipMemcpy(&nloc, q.loc_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+  PP_TRY(read_i32(q.loc_ptr + n, &nloc));
   PP_TRY(g_alloc(g, (void**)&q.loc_idx, sizeof(uint16_t) * (nloc + 4)));  // word copies may overrun by one
-  k_fill_local<<<gb, 256, 0, st>>>(n, g->col_ptr, g->row_idx, q.pid, g->part_ptr, q.loc_ptr, q.loc_idx);
+  k_fill_local<<<gb, 256, 0, st>>>(n, g->col_ptr, g->row_idx, q.pid, g->part_ptr, q.inv, q.loc_ptr, q.loc_idx);
+  {
+    int32_t* mx = nullptr;
+    PP_TRY(temp((void**)&mx, sizeof(int32_t)));
+    PP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
+    k_part_max_edges<<<grid_for(K, 256, 1024), 256, 0, st>>>(K, g->part_ptr, q.loc_ptr, mx);
+    PP_TRY(hipGetLastError());
+    PP_TRY(read_i32(mx, &q.max_local_edges));
+  }
+  // external in-links per row: light rows stream them, heavy rows become items
   k_count_ext<<<gw, 256, 0, st>>>(n, g->row_ptr, g->csr_col, q.pid, cnt, cnt2);
   PP_TRY(hipGetLastError());
-  rc = scan_exclusive_i32(c, cnt, n, light_ptr, g);
-  if (!rc) rc = scan_exclusive_i32(c, cnt2, n, heavy_ptr, g);
-  if (rc) { cleanup(); return rc; }
+  PP_RC(scan_exclusive_i32(c, cnt, n, light_ptr, g));
+  PP_RC(scan_exclusive_i32(c, cnt2, n, heavy_ptr, g));
   int32_t nlight = 0, nheavy_e = 0;
-  PP_TRY(hipMemcpy(&nlight, light_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
-  PP_TRY(hipMemcpy(&nheavy_e, heavy_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost));
+  PP_TRY(read_i32(light_ptr + n, &nlight));
+  PP_TRY(read_i32(heavy_ptr + n, &nheavy_e));
   PP_TRY(g_alloc(g, (void**)&q.ext_src, sizeof(int32_t) * std::max(1, nlight)));
   PP_TRY(g_alloc(g, (void**)&q.ext_row, sizeof(uint16_t) * std::max(1, nlight)));
   PP_TRY(g_alloc(g, (void**)&q.heavy_src, sizeof(int32_t) * std::max(1, nheavy_e)));
   PP_TRY(g_alloc(g, (void**)&q.ext_ptr, sizeof(int32_t) * (K + 1)));
-  k_fill_ext<<<gw, 256, 0, st>>>(n, g->row_ptr, g->csr_col, q.pid, g->part_ptr, light_ptr, heavy_ptr,
+  k_fill_ext<<<gw, 256, 0, st>>>(n, g->row_ptr, g->csr_col, q.pid, q.inv, light_ptr, heavy_ptr,
                                  q.ext_src, q.ext_row, q.heavy_src);
   k_gather_ptr<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, g->part_ptr, light_ptr, q.ext_ptr);
   PP_TRY(hipGetLastError());
-  // heavy rows (sorted) and their chunks; per-partition ranges of the heavy list
-  int* hcount = &c->ctrl->err;
-  PP_TRY(hipMemsetAsync(hcount, 0, sizeof(int), st));
-  PP_TRY(g_alloc(g, (void**)&q.heavy_rows, sizeof(int32_t) * std::max<int64_t>(1, n)));
-  k_heavy_list<<<gb, 256, 0, st>>>(n, heavy_ptr, q.heavy_rows, hcount);
-  int nh = 0;
-  PP_TRY(hipMemcpyAsync(&nh, hcount, sizeof(int), hipMemcpyDeviceToHost, st));
-  PP_TRY(hipStreamSynchronize(st));
-  std::vector<int32_t> rows(nh);
-  if (nh > 0) {
-    PP_TRY(hipMemcpy(rows.data(), q.heavy_rows, sizeof(int32_t) * nh, hipMemcpyDeviceToHost));
-    std::sort(rows.begin(), rows.end());
-    PP_TRY(hipMemcpy(q.heavy_rows, rows.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice));
-  }
-  std::vector<int32_t> ph(K + 1);
-  {
-    size_t r = 0;
-    for (int k = 0; k <= K; ++k) {
-      const int64_t lo = g->part_ptr_host[k];
-      while (r < rows.size() && rows[r] < lo) ++r;
-      ph[k] = (int32_t)r;
-    }
-  }
-  {
-    // heavy items: the external in-links of each heavy row cut in pieces of
-    // kItem, grouped by partition (heavy rows ascend, partitions are ranges)
-    std::vector<int32_t> hp(n + 1);
-    PP_TRY(hipMemcpyAsync(hp.data(), heavy_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
-    PP_TRY(hipStreamSynchronize(st));
-    std::vector<int32_t> irow, ibeg, iend, pit(K + 1);
-    size_t r = 0;
-    for (int k = 0; k < K; ++k) {
-      pit[k] = (int32_t)irow.size();
-      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
-      for (; r < rows.size() && rows[r] < hi; ++r)
-        for (int32_t b = hp[rows[r]]; b < hp[rows[r] + 1]; b += kItem) {
-          irow.push_back((int32_t)(rows[r] - lo));
-          ibeg.push_back(b);
-          iend.push_back(std::min(b + kItem, hp[rows[r] + 1]));
-        }
-    }
-    pit[K] = (int32_t)irow.size();
-    q.n_items = (int32_t)irow.size();
-    if (q.n_items >= (1 << 27)) {
-      cleanup();
-      return set_error(DITR_EINVAL, "too many heavy items (%d)", q.n_items);
-    }
-    // work units: an item takes a group of 2^l lanes, the fewest whose eight
-    // slots hold its links; groups are packed largest first, so each starts at
-    // a multiple of its size inside its unit
-    std::vector<int32_t> hsrc(std::max(1, nheavy_e));
-    if (nheavy_e > 0) PP_TRY(hipMemcpy(hsrc.data(), q.heavy_src, sizeof(int32_t) * nheavy_e, hipMemcpyDeviceToHost));
-    const int32_t ni = q.n_items;
-    std::vector<int> lg2(ni);
-    for (int32_t k = 0; k < ni; ++k) {
-      int l = 0;
-      while ((8 << l) < iend[k] - ibeg[k]) ++l;
-      lg2[k] = l;
-    }
-    std::vector<int32_t> by(ni);
-    for (int32_t k = 0; k < ni; ++k) by[k] = k;
-    std::stable_sort(by.begin(), by.end(), [&](int32_t x, int32_t y) { return lg2[x] > lg2[y]; });
-    std::vector<int32_t> usrc, umeta;
-    int lane = 64;
-    int64_t nu = 0;
-    for (int32_t k : by) {
-      const int gl = 1 << lg2[k];
-      if (lane + gl > 64) {
-        ++nu;
-        usrc.resize((size_t)nu * 512, -1);
-        umeta.resize((size_t)nu * 64, 0);
-        lane = 0;
-      }
-      const size_t u = (size_t)nu - 1;
-      for (int l = 0; l < gl; ++l) {
-        umeta[u * 64 + lane + l] = ((l == 0 ? k + 1 : 0) << 3) | lg2[k];
-        for (int qq = 0; qq < 8; ++qq) {
-          const int32_t e = ibeg[k] + l + gl * qq;
-          usrc[u * 512 + (size_t)qq * 64 + lane + l] = e < iend[k] ? hsrc[e] : -1;
-        }
-      }
-      lane += gl;
-    }
-    q.n_units = (int32_t)nu;
-    auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
-      HIP_TRY(g_alloc(g, (void**)dst, sizeof(int32_t) * std::max<size_t>(1, v.size())));
-      if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice));
-      return DITR_OK;
-    };
-    int urc = up(&q.item_row, irow);
-    if (!urc) urc = up(&q.part_items, pit);
-    if (!urc) urc = up(&q.unit_src, usrc);
-    if (!urc) urc = up(&q.unit_meta, umeta);
-    if (urc) { cleanup(); return urc; }
-    PP_TRY(g_alloc(g, (void**)&q.item_word, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
-    PP_TRY(hipMemset(q.item_word, 0, sizeof(unsigned long long) * 2 * std::max<size_t>(1, irow.size())));
-    // the unit table replaces the per-row source list
-    g_free(g, q.heavy_src);
-    q.heavy_src = nullptr;
-  }
-  q.n_heavy = nh;
+
+  // heavy rows, ascending (a scan of the heavy flags), and each partition's
+  // range of them
+  int32_t *hflag, *hpos;
+  PP_TRY(temp((void**)&hflag, sizeof(int32_t) * (n + 1)));
+  PP_TRY(temp((void**)&hpos, sizeof(int32_t) * (n + 1)));
+  k_heavy_flag<<<gb, 256, 0, st>>>(n, heavy_ptr, hflag);
+  PP_TRY(hipGetLastError());
+  PP_RC(scan_exclusive_i32(c, hflag, n, hpos, g));
+  int32_t nh = 0;
+  PP_TRY(read_i32(hpos + n, &nh));
+  PP_TRY(g_alloc(g, (void**)&q.heavy_rows, sizeof(int32_t) * std::max(1, nh)));
   PP_TRY(g_alloc(g, (void**)&q.part_heavy, sizeof(int32_t) * (K + 1)));
-  PP_TRY(hipMemcpy(q.part_heavy, ph.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice));
+  k_heavy_rows<<<gb, 256, 0, st>>>(n, hflag, hpos, q.heavy_rows);
+  k_gather_ptr<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, g->part_ptr, hpos, q.part_heavy);
+  PP_TRY(hipGetLastError());
+
+  // heavy items: the external in-links of each heavy row cut in pieces of
+  // kItem, in heavy-row order (so grouped by partition)
+  int32_t *icnt, *ioff;
+  PP_TRY(temp((void**)&icnt, sizeof(int32_t) * (std::max(1, nh) + 1)));
+  PP_TRY(temp((void**)&ioff, sizeof(int32_t) * (std::max(1, nh) + 1)));
+  k_item_count<<<grid_for(std::max(1, nh), 256, 8192), 256, 0, st>>>(nh, q.heavy_rows, heavy_ptr, icnt);
+  PP_TRY(hipGetLastError());
+  PP_RC(scan_exclusive_i32(c, icnt, nh, ioff, g));
+  int32_t ni = 0;
+  PP_TRY(read_i32(ioff + nh, &ni));
+  if (ni >= (1 << 27)) {
+    cleanup();
+    return set_error(DITR_EINVAL, "too many heavy items (%d)", ni);
+  }
+  q.n_items = ni;
+  const int ni1 = std::max(1, ni);
+  int32_t *ibeg, *iend, *by_in, *by;
+  uint32_t *ikey_in, *ikey;
+  PP_TRY(g_alloc(g, (void**)&q.item_row, sizeof(int32_t) * ni1));
+  PP_TRY(g_alloc(g, (void**)&q.part_items, sizeof(int32_t) * (K + 1)));
+  PP_TRY(temp((void**)&ibeg, sizeof(int32_t) * ni1));
+  PP_TRY(temp((void**)&iend, sizeof(int32_t) * ni1));
+  PP_TRY(temp((void**)&by_in, sizeof(int32_t) * ni1));
+  PP_TRY(temp((void**)&by, sizeof(int32_t) * ni1));
+  PP_TRY(temp((void**)&ikey_in, sizeof(uint32_t) * ni1));
+  PP_TRY(temp((void**)&ikey, sizeof(uint32_t) * ni1));
+  k_item_fill<<<grid_for(std::max(1, nh), 256, 8192), 256, 0, st>>>(nh, q.heavy_rows, heavy_ptr, ioff, q.inv,
+                                                                   q.item_row, ibeg, iend, ikey_in, by_in);
+  k_gather_ptr2<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, q.part_heavy, ioff, q.part_items);
+  PP_TRY(hipGetLastError());
+
+  // work units: an item takes a group of 2^l lanes, the fewest whose eight
+  // slots hold its links. Groups are packed largest first (a stable sort by
+  // size class), so each starts at a multiple of its size and a unit is full
+  // before the next one starts: the lane of every group is a prefix sum.
+  int32_t *gl, *loff;
+  PP_TRY(temp((void**)&gl, sizeof(int32_t) * (ni1 + 1)));
+  PP_TRY(temp((void**)&loff, sizeof(int32_t) * (ni1 + 1)));
+  if (ni > 0) {
+    size_t tb = 0;
+    PP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, ikey_in, ikey, by_in, by, ni, 0, 3, st));
+    void* tmp = nullptr;
+    PP_TRY(temp(&tmp, tb));
+    PP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, ikey_in, ikey, by_in, by, ni, 0, 3, st));
+    k_unit_lanes<<<grid_for(ni, 256, 8192), 256, 0, st>>>(ni, by, ibeg, iend, gl);
+    PP_TRY(hipGetLastError());
+  }
+  PP_RC(scan_exclusive_i32(c, gl, ni, loff, g));
+  int32_t lanes = 0;
+  PP_TRY(read_i32(loff + ni, &lanes));
+  const int64_t nu = ((int64_t)lanes + 63) / 64;
+  q.n_units = (int32_t)nu;
+  PP_TRY(g_alloc(g, (void**)&q.unit_src, sizeof(int32_t) * 512 * std::max<int64_t>(1, nu)));
+  PP_TRY(g_alloc(g, (void**)&q.unit_meta, sizeof(int32_t) * 64 * std::max<int64_t>(1, nu)));
+  k_fill_i32p<<<grid_for(512 * std::max<int64_t>(1, nu), 256, 8192), 256, 0, st>>>(q.unit_src, 512 * std::max<int64_t>(1, nu), -1);
+  k_fill_i32p<<<grid_for(64 * std::max<int64_t>(1, nu), 256, 8192), 256, 0, st>>>(q.unit_meta, 64 * std::max<int64_t>(1, nu), 0);
+  if (ni > 0)
+    k_unit_fill<<<grid_for(ni, 256, 8192), 256, 0, st>>>(ni, by, loff, ibeg, iend, q.heavy_src, q.unit_src,
+                                                         q.unit_meta);
+  PP_TRY(hipGetLastError());
+  PP_TRY(g_alloc(g, (void**)&q.item_word, sizeof(unsigned long long) * 2 * ni1));
+  PP_TRY(hipMemsetAsync(q.item_word, 0, sizeof(unsigned long long) * 2 * ni1, st));
+  q.n_heavy = nh;
+
   PP_TRY(g_alloc(g, (void**)&q.pw, sizeof(float) * n));
-  PP_TRY(g_alloc(g, (void**)&q.ext_deg, sizeof(int32_t) * n));
-  k_weights<<<gb, 256, 0, st>>>(n, g->col_ptr, q.loc_ptr, (float)g->d, q.pw, q.ext_deg);
+  k_weights<<<gb, 256, 0, st>>>(n, g->col_ptr, (float)g->d, q.pw);
   PP_TRY(hipGetLastError());
   PP_TRY(g_alloc(g, (void**)&q.S, sizeof(float) * 2 * n));
   PP_TRY(g_alloc(g, (void**)&q.counters, sizeof(int) * kCounters));
-  PP_TRY(hipMemset(q.counters, 0, sizeof(int) * kCounters));
+  PP_TRY(hipMemsetAsync(q.counters, 0, sizeof(int) * kCounters, st));
   PP_TRY(g_alloc(g, (void**)&q.partials, sizeof(double) * kStride * 2 * K));
-  {
-    std::vector<int32_t> lp(K + 1);
-    int32_t* d_lp = nullptr;
-    PP_TRY(g_alloc(g, (void**)&d_lp, sizeof(int32_t) * (K + 1)));
-    k_gather_ptr<<<grid_for(K + 1, 256, 1024), 256, 0, st>>>(K, g->part_ptr, q.loc_ptr, d_lp);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(lp.data(), d_lp, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    g_free(g, d_lp);
-    PP_TRY(e);
-    int32_t mx = 0;
-    for (int k = 0; k < K; ++k) mx = std::max(mx, lp[k + 1] - lp[k]);
-    q.max_local_edges = mx;
-  }
-  {
-    // visiting order of each partition's nodes: falling local out-degree
-    // (stable counting sort), so that the 64 lanes of a wave push lists of
-    // about the same length (computed on the CSC in node order)
-    std::vector<int32_t> lp(n + 1);
-    PP_TRY(hipMemcpyAsync(lp.data(), q.loc_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
-    PP_TRY(hipStreamSynchronize(st));
-    std::vector<uint16_t> ord(n);
-    std::vector<int32_t> cnt;
-    for (int64_t k = 0; k < K; ++k) {
-      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
-      int32_t dmax = 0;
-      for (int64_t i = lo; i < hi; ++i) dmax = std::max(dmax, lp[i + 1] - lp[i]);
-      cnt.assign((size_t)dmax + 2, 0);
-      for (int64_t i = lo; i < hi; ++i) ++cnt[dmax - (lp[i + 1] - lp[i]) + 1];
-      for (int32_t b = 1; b <= dmax + 1; ++b) cnt[b] += cnt[b - 1];
-      for (int64_t i = lo; i < hi; ++i) ord[lo + cnt[dmax - (lp[i + 1] - lp[i])]++] = (uint16_t)(i - lo);
-    }
-    // renumber each partition's nodes by that order: local id r is node
-    // lo + order[lo + r]; the local CSC, the rows of the light external links
-    // and the rows of the heavy items take the new ids
-    std::vector<uint16_t> inv(n);
-    for (int64_t k = 0; k < K; ++k) {
-      const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
-      for (int64_t r = 0; r < hi - lo; ++r) inv[lo + ord[lo + r]] = (uint16_t)r;
-    }
-    PP_TRY(g_alloc(g, (void**)&q.inv, sizeof(uint16_t) * std::max<int64_t>(1, n)));
-    PP_TRY(hipMemcpy(q.inv, inv.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice));
-    {
-      std::vector<uint16_t> li((size_t)nloc + 4), li2((size_t)nloc + 4, 0);
-      PP_TRY(hipMemcpy(li.data(), q.loc_idx, sizeof(uint16_t) * nloc, hipMemcpyDeviceToHost));
-      std::vector<int32_t> lp2(n + 1);
-      for (int64_t k = 0; k < K; ++k) {
-        const int64_t lo = g->part_ptr_host[k], hi = g->part_ptr_host[k + 1];
-        int32_t pos = lp[lo];
-        for (int64_t r = 0; r < hi - lo; ++r) {
-          const int64_t i = lo + ord[lo + r];
-          lp2[lo + r] = pos;
-          for (int32_t e = lp[i]; e < lp[i + 1]; ++e) li2[pos++] = inv[lo + li[e]];
-        }
-      }
-      lp2[n] = lp[n];
-      PP_TRY(hipMemcpy(q.loc_ptr, lp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
-      PP_TRY(hipMemcpy(q.loc_idx, li2.data(), sizeof(uint16_t) * nloc, hipMemcpyHostToDevice));
-    }
-    {
-      std::vector<int32_t> ep(K + 1);
-      std::vector<uint16_t> er(std::max(1, nlight));
-      PP_TRY(hipMemcpy(ep.data(), q.ext_ptr, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost));
-      if (nlight > 0) PP_TRY(hipMemcpy(er.data(), q.ext_row, sizeof(uint16_t) * nlight, hipMemcpyDeviceToHost));
-      for (int64_t k = 0; k < K; ++k)
-        for (int32_t e = ep[k]; e < ep[k + 1]; ++e) er[e] = inv[g->part_ptr_host[k] + er[e]];
-      if (nlight > 0) PP_TRY(hipMemcpy(q.ext_row, er.data(), sizeof(uint16_t) * nlight, hipMemcpyHostToDevice));
-    }
-    if (q.n_items > 0) {
-      std::vector<int32_t> pi(K + 1), ir(q.n_items);
-      PP_TRY(hipMemcpy(pi.data(), q.part_items, sizeof(int32_t) * (K + 1), hipMemcpyDeviceToHost));
-      PP_TRY(hipMemcpy(ir.data(), q.item_row, sizeof(int32_t) * q.n_items, hipMemcpyDeviceToHost));
-      for (int64_t k = 0; k < K; ++k)
-        for (int32_t t = pi[k]; t < pi[k + 1]; ++t) ir[t] = inv[g->part_ptr_host[k] + ir[t]];
-      PP_TRY(hipMemcpy(q.item_row, ir.data(), sizeof(int32_t) * q.n_items, hipMemcpyHostToDevice));
-    }
-  }
+  PP_TRY(hipStreamSynchronize(st));
+  // the unit table replaces the per-row source list
+  temps.push_back(q.heavy_src);
+  q.heavy_src = nullptr;
   q.n_local = nloc;
   q.n_ext = nlight;
   q.n_heavy_edges = nheavy_e;
   cleanup();
   q.ready = true;
 #undef PP_TRY
+#undef PP_RC
   return DITR_OK;
 }
 
@@ -1399,8 +1476,6 @@ int part_args(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, d
   a.loc_ptr = q.loc_ptr;
   a.loc_idx = q.loc_idx;
   a.inv = q.inv;
-  a.pw = q.pw;
-  a.ext_deg = q.ext_deg;
   a.ext_ptr = q.ext_ptr;
   a.ext_src = q.ext_src;
   a.ext_row = q.ext_row;
