@@ -164,6 +164,9 @@ def trace_summary(ctx, g, bt, ht, ft, tol, opts, K, dev):
         "busy_us_max_over_mean": float((busy.max(axis=1) / busy.mean(axis=1)).mean()),
         "level_us_mean": float(1e6 * level_s.mean()),
         "sent_share_mean": float((sent.sum(axis=1) / (held + sent).sum(axis=1)).mean()),
+        # nodes diffused per level over all nodes: nearly every node diffuses at
+        # every level, so per-level work cannot skip quiet partitions
+        "diffused_share_per_level": float(rec[..., 2].sum(axis=1).mean() / bt.numel()),
         "fluid_decay_per_level": float(np.exp(np.mean(np.diff(np.log((held + sent).sum(axis=1)))))),
         "idle_polls": int(st.idle_polls),
         "note": "traced solve (a separate kernel instantiation), not part of the timed steps",
@@ -190,6 +193,15 @@ def batched_bench(ctx, g, n, dev):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     worst = max(p.resid_l1 / p.b_l1 for p in per)
+    # the batched schedule picked by the library's tuner (alpha, first refresh;
+    # untimed search), then one timed batch with it
+    tuned, tinfo = ditr.tune_batched(ctx, g, B, H, F, rel_tol=tol, effort=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_t, per_t = ditr.solve_batched(ctx, g, B, H, F, rel_tol=tol, opts=tuned, allow=(ditr.OK,))
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - t0
+    worst_t = max(p.resid_l1 / p.b_l1 for p in per_t)
     del H, F
     # plain solves of every column, one at a time
     cols = list(range(R))
@@ -223,6 +235,15 @@ def batched_bench(ctx, g, n, dev):
         "batched_edges_per_rhs": tot.edges / R,
         "worst_resid_rel": worst,
         "rounds": tot.rounds,
+        "tuned": {
+            "alpha": tuned.alpha,
+            "refresh_at": tuned.refresh_at,
+            "batched_ms": 1e3 * t_tuned,
+            "speedup_per_rhs": plain / (t_tuned / R),
+            "worst_resid_rel": worst_t,
+            "tuner_candidates": tinfo.candidates,
+            "tuner_seconds": tinfo.seconds,
+        },
     }
 
 

@@ -117,10 +117,13 @@ typedef struct {
 typedef struct {
   int64_t edges;       /* elementary edge diffusions (Section 2.4: normalized iterations x L) */
   int64_t diffusions;  /* node diffusions */
-  int64_t sweeps;      /* partition sweeps summed over workgroups (persistent) or grid sweeps */
+  int64_t sweeps;      /* PARTITION: threshold levels; ASYNC: partition sweeps summed over
+                          workgroups; SWEEP: grid sweeps */
   int64_t launches;    /* diffusion kernel launches */
   int64_t refreshes;   /* exact FP64 residual refreshes F = B + P H - H */
-  int64_t idle_polls;  /* polls of an idle workgroup on its inbox (Section 3.3 idle time) */
+  int64_t idle_polls;  /* polls that found nothing yet (Section 3.3 idle time): ASYNC, an idle
+                          workgroup on its inbox; PARTITION (resident), a partition waiting
+                          for the others to finish the previous level */
   double resid_l1;     /* final exact ||F||_1 (FP64, from the last refresh) */
   double b_l1;         /* ||B||_1 */
   double seconds;      /* host wall time of the call */
@@ -336,6 +339,20 @@ int ditr_tune(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
               const int32_t* d_row_idx, double damping, const double* d_b, double* d_h, float* d_f,
               double rel_tol, int effort, const char* cache_path, ditr_opts* out,
               ditr_tune_info* info);
+/* Pick the options of the batched solve (ditr_solve_batched) that reach
+ * rel_tol ||B_r||_1 for every right-hand side fastest on this graph and these
+ * right-hand sides: the threshold divisor alpha of every right-hand side's
+ * schedule (Section 2.4; candidates 1.25, 1.5, 2, 3, 4) and, with effort >= 1,
+ * the first exact-refresh point (1e-5, 1e-6, 1e-7), by coordinate search over
+ * wall time (effort 2: a second pass). The batched sweep has no partition plan,
+ * so these are its schedule knobs. Arguments as ditr_solve_batched: d_b [n][nrhs]
+ * is read, d_h and d_f are work buffers (overwritten), the workspace is the
+ * caller's (NULL and 0: the library allocates per call). The returned options
+ * are never slower than the defaults at the final re-timing, else they are the
+ * defaults; info (may be NULL) gets the timings. No cache. Synchronizes. */
+int ditr_tune_batched(ditr_ctx* ctx, const ditr_graph* g, int nrhs, const double* d_b, double* d_h,
+                      float* d_f, double rel_tol, void* d_workspace, size_t ws_bytes, int effort,
+                      ditr_opts* out, ditr_tune_info* info);
 /* The cache key of a problem: a position-aware hash of col_ptr, row_idx and B
  * computed on the device, combined with n, nnz, damping, rel_tol and the
  * device's architecture name and CU count. Synchronizes. */

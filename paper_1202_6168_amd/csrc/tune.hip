@@ -540,4 +540,99 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
   return DITR_OK;
 }
 
+// Batched solve: the threshold schedule of every right-hand side (alpha) and
+// the first exact-refresh point, by wall time to tolerance of the whole batch.
+// The batched sweep has no partition plan, so these are its only schedule
+// knobs; the graph and the workspace are the caller's.
+int ditr_tune_batched(ditr_ctx* c, const ditr_graph* g, int nrhs, const double* d_b, double* d_h, float* d_f,
+                      double rel_tol, void* d_workspace, size_t ws_bytes, int effort, ditr_opts* out,
+                      ditr_tune_info* info) {
+  const double t_start = wall_now();
+  if (!c || !g || !d_b || !d_h || !d_f || !out) return set_error(DITR_EINVAL, "NULL argument");
+  if (!(rel_tol > 0) || !std::isfinite(rel_tol)) return set_error(DITR_EINVAL, "rel_tol must be > 0");
+  if (effort < 0 || effort > 2) return set_error(DITR_EINVAL, "effort must be 0, 1 or 2");
+  ditr_tune_info inf;
+  memset(&inf, 0, sizeof(inf));
+  ditr_opts base;
+  ditr_opts_default(&base);
+  base.flags = 0;
+  // best of reps timed batches with options o (+inf if a batch does not converge)
+  auto timed = [&](const ditr_opts& o, int reps, double* secs, int64_t* edges) -> int {
+    *secs = INFINITY;
+    *edges = 0;
+    for (int i = 0; i < reps; ++i) {
+      ditr_stats tot;
+      const double t0 = wall_now();
+      const int rc = ditr_solve_batched(c, g, nrhs, d_b, d_h, d_f, rel_tol, &o, d_workspace, ws_bytes, nullptr, &tot);
+      const double dt = wall_now() - t0;
+      inf.candidates += 1;
+      if (rc < 0) return rc;
+      if (rc != DITR_OK) return DITR_OK;  // did not converge: rejected
+      if (dt < *secs) {
+        *secs = dt;
+        *edges = tot.edges;
+      }
+    }
+    return DITR_OK;
+  };
+  double t_def = 0;
+  int64_t e_def = 0;
+  int rc = timed(base, 1, &t_def, &e_def);  // also warms the workspace and the code
+  if (rc) return rc;
+  if (!std::isfinite(t_def)) return set_error(DITR_NOT_CONVERGED, "default options do not converge");
+  const int reps = t_def > 0.25 ? 1 : 2;
+  ditr_opts best = base;
+  double t_best = INFINITY;
+  int64_t e_best = 0;
+  if ((rc = timed(base, reps, &t_best, &e_best))) return rc;
+  const double margin = 0.97;
+  auto consider = [&](const ditr_opts& o) -> int {
+    double t;
+    int64_t ed;
+    const int r = timed(o, reps, &t, &ed);
+    if (r) return r;
+    if (t < margin * t_best) {
+      best = o;
+      t_best = t;
+      e_best = ed;
+    }
+    return DITR_OK;
+  };
+  const int passes = effort == 2 ? 2 : 1;
+  for (int pass = 0; pass < passes; ++pass) {
+    for (double a : {1.25, 1.5, 2.0, 3.0, 4.0}) {
+      if (a == best.alpha) continue;
+      ditr_opts o = best;
+      o.alpha = a;
+      if ((rc = consider(o))) return rc;
+    }
+    if (effort == 0) break;
+    for (double ra : {1e-5, 1e-6, 1e-7}) {
+      if (ra == best.refresh_at) continue;
+      ditr_opts o = best;
+      o.refresh_at = ra;
+      if ((rc = consider(o))) return rc;
+    }
+  }
+  // re-time the winner against the defaults
+  double t_def2, t_win;
+  int64_t e_def2, e_win;
+  const int final_reps = std::max(reps, 2);
+  if ((rc = timed(base, final_reps, &t_def2, &e_def2))) return rc;
+  if ((rc = timed(best, final_reps, &t_win, &e_win))) return rc;
+  if (!(t_win < t_def2)) {
+    best = base;
+    t_win = t_def2;
+    e_win = e_def2;
+  }
+  inf.default_seconds = t_def2;
+  inf.default_edges = e_def2;
+  inf.best_seconds = t_win;
+  inf.best_edges = e_win;
+  *out = best;
+  inf.seconds = wall_now() - t_start;
+  if (info) *info = inf;
+  return DITR_OK;
+}
+
 }  // extern "C"

@@ -147,6 +147,8 @@ _SIGNATURES = {
     "ditr_graph_workspace_used": ([_vp, ctypes.POINTER(ctypes.c_size_t)], _i32),
     "ditr_tune": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _vp, _vp, _dbl, _i32, ctypes.c_char_p,
                    ctypes.POINTER(Opts), ctypes.POINTER(TuneInfo)], _i32),
+    "ditr_tune_batched": ([_vp, _vp, _i32, _vp, _vp, _vp, _dbl, _vp, ctypes.c_size_t, _i32,
+                           ctypes.POINTER(Opts), ctypes.POINTER(TuneInfo)], _i32),
     "ditr_tune_key": ([_vp, _i64, _i64, _vp, _vp, _dbl, _vp, _dbl,
                        ctypes.POINTER(ctypes.c_uint64)], _i32),
     "ditr_tune_cache_get": ([ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(Opts)], _i32),
@@ -515,6 +517,24 @@ def tune(ctx: Context, col_ptr, row_idx, b, h, f, rel_tol: float = 1e-9, effort:
                           damping, _ptr(b), _ptr(h), _ptr(f), rel_tol, effort,
                           cache_path.encode() if cache_path else None, ctypes.byref(o),
                           ctypes.byref(info)))
+    return o, info
+
+
+def tune_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, effort: int = 1,
+                 workspace=None):
+    """ditr_tune_batched: options (alpha, first refresh point) of the fastest batched
+    solve of these [n, R] right-hand sides on g; returns (opts, info). h and f are
+    work buffers (overwritten)."""
+    torch = ctx.torch
+    if b.dtype != torch.float64 or h.dtype != torch.float64 or f.dtype != torch.float32:
+        raise TypeError("b, h must be float64 and f float32")
+    if b.dim() != 2 or b.shape[0] != g.n or h.shape != b.shape or f.shape != b.shape:
+        raise ValueError("b, h, f must be [n, R] with the same shape")
+    R = b.shape[1]
+    ws = workspace if workspace is not None else g.batch_workspace(R)
+    o, info = Opts(), TuneInfo()
+    check(lib().ditr_tune_batched(ctx.handle, g.handle, R, _ptr(b), _ptr(h), _ptr(f), rel_tol,
+                                  _ptr(ws), ws.numel(), effort, ctypes.byref(o), ctypes.byref(info)))
     return o, info
 
 

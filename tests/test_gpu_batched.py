@@ -188,3 +188,32 @@ def test_batched_headline_size_256(ctx):
     del bt, ht, ft
     g.close()
     check_columns(cp, ri, B, H, F, per, tol, cols)
+
+
+def test_batched_tuner_keeps_parity(ctx):
+    """ditr_tune_batched picks alpha and the first refresh point by time; the
+    options it returns still give oracle parity on every checked column, and
+    it never returns options slower than the defaults at its final re-timing."""
+    spec = ditgen.GraphSpec(n=20_000, block=1000, seed=6)
+    cp, ri = ditgen.generate(spec)
+    R = 16
+    B = ditgen.ppr_rhs_dense(spec.n, ditgen.ppr_seed_sets(spec.n, R, seed=9))
+    dev = torch.device("cuda", 0)
+    g = ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev))
+    bt = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    ht = torch.empty_like(bt)
+    ft = torch.empty(B.shape, dtype=torch.float32, device=dev)
+    o, info = ditr.tune_batched(ctx, g, bt, ht, ft, rel_tol=1e-8, effort=1)
+    assert info.candidates >= 8
+    assert info.best_seconds <= info.default_seconds
+    assert o.alpha in (1.25, 1.5, 2.0, 3.0, 4.0)
+    assert o.refresh_at in (0.0, 1e-5, 1e-6, 1e-7)
+    tot, per = ditr.solve_batched(ctx, g, bt, ht, ft, rel_tol=1e-8, opts=o)
+    torch.cuda.synchronize()
+    H, F = ht.cpu().numpy(), ft.cpu().numpy().astype(np.float64)
+    g.close()
+    assert tot.status == ditr.OK
+    check_columns(cp, ri, B, H, F, per, 1e-8, [0, 5, R - 1])
+    with pytest.raises(ditr.DitrError):
+        ditr.tune_batched(ctx, ditr.Graph(ctx, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)),
+                          bt, ht, ft, rel_tol=-1.0)
