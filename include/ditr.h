@@ -197,6 +197,37 @@ int ditr_graph_upload_csc(ditr_ctx* ctx, ditr_graph** out, int64_t n, int64_t nn
 /* Workspace bytes an uploaded graph actually used (0 for ditr_graph_create). */
 int ditr_graph_workspace_used(const ditr_graph* g, size_t* used);
 
+/* Replace the partition plan of g by the boundaries h_ptr[0..K] (host, 0 =
+ * h_ptr[0] <= ... <= h_ptr[K] = n) and rebuild its tables (Section 2.3: any
+ * node-set partition is valid). DITR_EINVAL if a part exceeds the nodes one
+ * workgroup holds in LDS, or for a graph uploaded into a caller workspace
+ * (which keeps its plan). Synchronizes. */
+int ditr_graph_set_partitions(ditr_ctx* ctx, ditr_graph* g, const int64_t* h_ptr, int64_t K);
+
+typedef struct {
+  int32_t rounds;         /* adaptation rounds run */
+  int32_t kept;           /* rounds whose plan was kept (the solve got faster) */
+  double seconds_before;  /* best of 3 solves to tolerance with the plan on entry */
+  double seconds_after;   /* the same with the plan on return (<= seconds_before) */
+  double spread_before;   /* slowest partition's mean work per level over the mean, on entry */
+  double spread_after;    /* the same on return */
+  double seconds;         /* host wall time of the call */
+} ditr_adapt_info;
+
+/* Partition adaptation (Section 3.4, where the boundary between two PIDs moves
+ * towards the one that does more work): time the partitioned solve of
+ * (d_b, rel_tol) on g, trace each partition's work per level (ditr_set_trace),
+ * move every boundary a fraction omega (0 < omega <= 1) of the way to the
+ * points that split the measured work into K equal parts (a partition's nodes
+ * share its work evenly), rebuild the plan and time again. A plan is kept only
+ * if the solve is at least 0.5% faster; otherwise the previous one is restored
+ * and the adaptation stops. At most `rounds` rounds (0..64). d_h and d_f are
+ * work buffers (overwritten). DITR_EINVAL for a general matrix (solved by the
+ * pull sweep, which has no partitions) or a graph in a caller workspace.
+ * `info` may be NULL. Synchronizes. */
+int ditr_graph_adapt(ditr_ctx* ctx, ditr_graph* g, const double* d_b, double* d_h, float* d_f,
+                     double rel_tol, int rounds, double omega, ditr_adapt_info* info);
+
 /* Number of partitions K of the plan and, if h_ptr != NULL and cap >= K+1,
  * the boundaries omega_0 = 0 < ... <= omega_K = n. Synchronizes. */
 int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, int64_t cap);

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -244,6 +245,47 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
 
 }  // extern "C"
 
+// Replace the partition boundaries of g by h_ptr (K + 1 nondecreasing values
+// from 0 to n, no part above g->cap_nodes) and rebuild the partition tables.
+int graph_set_plan(ditr_ctx* c, ditr_graph* g, const int64_t* h_ptr, int64_t K) {
+  if (!c || !g || !h_ptr) return set_error(DITR_EINVAL, "NULL argument");
+  if (g->arena.base)
+    return set_error(DITR_EINVAL, "a graph in a caller workspace keeps the plan it was uploaded with");
+  if (K < 1 || K > g->n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
+  if (h_ptr[0] != 0 || h_ptr[K] != g->n) return set_error(DITR_EINVAL, "boundaries must run from 0 to n");
+  int64_t mx = 0;
+  for (int64_t k = 0; k < K; ++k) {
+    if (h_ptr[k + 1] < h_ptr[k]) return set_error(DITR_EINVAL, "boundaries must not decrease");
+    mx = std::max(mx, h_ptr[k + 1] - h_ptr[k]);
+  }
+  if (mx > g->cap_nodes)
+    return set_error(DITR_EINVAL, "a partition of %lld nodes exceeds the %lld one workgroup holds", (long long)mx,
+                     (long long)g->cap_nodes);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  free_part_plan(g);
+  g_free(g, g->part_ptr);
+  g_free(g, g->part_T);
+  g_free(g, g->part_lock);
+  g->part_ptr = nullptr;
+  g->part_T = nullptr;
+  g->part_lock = nullptr;
+  delete[] g->part_ptr_host;
+  g->part_ptr_host = new (std::nothrow) int64_t[K + 1];
+  if (!g->part_ptr_host) return set_error(DITR_ENOMEM, "host allocation failed");
+  memcpy(g->part_ptr_host, h_ptr, sizeof(int64_t) * (K + 1));
+  g->K = K;
+  g->max_part = (int32_t)mx;
+  std::vector<int32_t> p32(K + 1);
+  for (int64_t k = 0; k <= K; ++k) p32[k] = (int32_t)h_ptr[k];
+  HIP_TRY(g_alloc(g, (void**)&g->part_ptr, sizeof(int32_t) * (K + 1)));
+  HIP_TRY(g_alloc(g, (void**)&g->part_T, sizeof(double) * K));
+  HIP_TRY(g_alloc(g, (void**)&g->part_lock, sizeof(int) * K));
+  HIP_TRY(hipMemsetAsync(g->part_lock, 0, sizeof(int) * K, c->stream));
+  HIP_TRY(hipMemcpy(g->part_ptr, p32.data(), sizeof(int32_t) * (K + 1), hipMemcpyHostToDevice));
+  return build_part_plan(c, g);
+}
+
 // Graph upload for the PageRank matrix (d_val == nullptr, p_ji = damping / #out_i)
 // or a general matrix (one weight per CSC entry, Section 2).
 static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t nnz,
@@ -339,6 +381,7 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
   // (12 bytes per node for the asynchronous one, 20 for the partitioned sweep)
   const int64_t cap_nodes = std::min<int64_t>(
       65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 20)));
+  g->cap_nodes = cap_nodes;
   int64_t K;
   if (o.part_nodes > 0) {
     K = (n + o.part_nodes - 1) / o.part_nodes;

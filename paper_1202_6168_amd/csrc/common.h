@@ -121,6 +121,7 @@ struct ditr_graph {
   int32_t* part_ptr = nullptr;       // [K+1] device
   int64_t* part_ptr_host = nullptr;  // [K+1] host copy
   int32_t max_part = 0;              // nodes in the largest partition
+  int64_t cap_nodes = 0;             // nodes one partition may hold (LDS of the partition kernels)
   int part_type = DITR_PART_CB;
   double* part_T = nullptr;          // [K] per-partition threshold carried between claims
   int* part_lock = nullptr;          // [K] claim locks (dynamic binding)
@@ -296,6 +297,7 @@ void free_part_plan(ditr_graph* g);
 int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges, bool prio = false);
 size_t plan_sort_temp_bytes(int64_t n, int64_t ni);
+int graph_set_plan(ditr_ctx* c, ditr_graph* g, const int64_t* h_ptr, int64_t K);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
                         double target, double T0);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,

@@ -307,7 +307,7 @@ struct PartArgs {
   double tick_s;      // seconds per s_memrealtime tick
 };
 
-constexpr int kTrace = 6;  // doubles per trace record (DITR_TRACE_FIELDS)
+constexpr int kTrace = DITR_TRACE_FIELDS;  // doubles per trace record
 
 // thread 0 writes partition p's record of solve level `level` (if it fits)
 __device__ __forceinline__ void trace_write(const PartArgs& a, int64_t level, int p, double held, double sent,

@@ -81,6 +81,21 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class AdaptInfo(ctypes.Structure):
+    _fields_ = [
+        ("rounds", ctypes.c_int32),
+        ("kept", ctypes.c_int32),
+        ("seconds_before", ctypes.c_double),
+        ("seconds_after", ctypes.c_double),
+        ("spread_before", ctypes.c_double),
+        ("spread_after", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TuneInfo(ctypes.Structure):
     _fields_ = [
         ("key", ctypes.c_uint64),
@@ -128,6 +143,8 @@ _SIGNATURES = {
                                     ctypes.POINTER(Opts)], _i32),
     "ditr_graph_contraction": ([_vp, ctypes.POINTER(_dbl)], _i32),
     "ditr_graph_destroy": ([_vp], _i32),
+    "ditr_graph_set_partitions": ([_vp, _vp, _vp, _i64], _i32),
+    "ditr_graph_adapt": ([_vp, _vp, _vp, _vp, _vp, _dbl, _i32, _dbl, ctypes.POINTER(AdaptInfo)], _i32),
     "ditr_graph_partitions": ([_vp, ctypes.POINTER(_i64), _vp, _i64], _i32),
     "ditr_partition": ([_vp, _i64, _i64, _vp, _vp, _i32, _i64, _vp], _i32),
     "ditr_partition_pmass": ([_vp, _i64, _i64, _vp, _vp, _vp, _dbl, _i64, _vp], _i32),
@@ -378,6 +395,14 @@ class Graph:
                                           ctypes.c_void_p(out.ctypes.data), out.size))
         return out
 
+    def set_partitions(self, ptr):
+        """ditr_graph_set_partitions: new boundaries (K + 1 host int64 values) and tables."""
+        import numpy as np
+
+        p = np.ascontiguousarray(ptr, np.int64)
+        check(lib().ditr_graph_set_partitions(self.ctx.handle, self.handle, ctypes.c_void_p(p.ctypes.data),
+                                              p.size - 1))
+
     def close(self):
         if self.handle:
             lib().ditr_graph_destroy(self.handle)
@@ -518,6 +543,16 @@ def tune(ctx: Context, col_ptr, row_idx, b, h, f, rel_tol: float = 1e-9, effort:
                           cache_path.encode() if cache_path else None, ctypes.byref(o),
                           ctypes.byref(info)))
     return o, info
+
+
+def adapt(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-9, rounds: int = 4, omega: float = 0.5):
+    """ditr_graph_adapt: move g's partition boundaries towards equal measured work per
+    partition (Section 3.4) while the solve gets faster; returns AdaptInfo. h and f are
+    work buffers (overwritten)."""
+    info = AdaptInfo()
+    check(lib().ditr_graph_adapt(ctx.handle, g.handle, _ptr(b), _ptr(h), _ptr(f), rel_tol, rounds, omega,
+                                 ctypes.byref(info)))
+    return info
 
 
 def tune_batched(ctx: Context, g: Graph, b, h, f, rel_tol: float = 1e-8, effort: int = 1,
