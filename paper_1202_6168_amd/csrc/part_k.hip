@@ -996,11 +996,13 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     const bool aborted = levels > 0 && ld_agent(&prev[4]) != 0.0;  // workgroup 0's vote
     if (levels > 0)
       for (int k = tid; k < a.K; k += BLOCK) {
+        // the four loads first, then the uses (one wait instead of four)
         const double* q = prev + (size_t)kStride * k;
-        D += ld_agent(&q[0]);
-        M = fmax(M, ld_agent(&q[1]));
-        E += ld_agent(&q[2]);
-        P += ld_agent(&q[3]);
+        const double q0 = ld_agent(&q[0]), q1 = ld_agent(&q[1]), q2 = ld_agent(&q[2]), q3 = ld_agent(&q[3]);
+        D += q0;
+        M = fmax(M, q1);
+        E += q2;
+        P += q3;
       }
     if (unit0 < a.n_units) unit_finish<true>(a, L0, iv, epoch, ib);
     item_sums<true>(a, S_in, unit0 + n_waves, n_waves, epoch, ib);
