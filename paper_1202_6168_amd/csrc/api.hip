@@ -593,6 +593,9 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     return finish(set_error(DITR_EINVAL, "unknown mode %d", mode));
   if (noalloc && mode != DITR_MODE_PARTITION)
     return finish(set_error(DITR_EINVAL, "the allocation-free solve runs the partitioned sweep only"));
+  if (mode != DITR_MODE_SWEEP && (!g->part_ptr || !g->pp.ready))
+    return finish(set_error(DITR_EINVAL, "the graph has no partition plan (a failed ditr_graph_set_partitions); "
+                                         "set a valid one first"));
   const bool prio = (o.flags & DITR_FLAG_PRIORITY) != 0;
   if (prio && mode != DITR_MODE_PARTITION)
     return finish(set_error(DITR_EINVAL, "the normalized priority test runs in the partitioned sweep"));
