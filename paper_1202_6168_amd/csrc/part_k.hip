@@ -424,16 +424,18 @@ __device__ __forceinline__ PartView part_view(const PartArgs& a, unsigned char* 
 template <int BLOCK, bool PRIO>
 __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
   const int tid = threadIdx.x;
-  for (int i = tid; i < v.np; i += BLOCK) v.lptr[i] = a.loc_ptr[v.lo + i] - v.lbase;
   {
+    // position j of the partition: the local CSC offset of local id j, and
+    // the fluid and out-degree of node lo + j (at its local id)
     constexpr int U = 8;
     for (int j0 = tid; j0 < v.np; j0 += U * BLOCK) {
-      int r[U], c0[U], c1[U];
+      int r[U], c0[U], c1[U], lp[U];
       float f[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + u * BLOCK;
         if (j < v.np) {
+          lp[u] = a.loc_ptr[v.lo + j];
           r[u] = a.inv[v.lo + j];
           f[u] = a.F[v.lo + j];
           c0[u] = a.col_ptr[v.lo + j];
@@ -442,7 +444,9 @@ __device__ void part_load(const PartArgs& a, const PartView& v, double inv_q) {
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (j0 + u * BLOCK < v.np) {
+        const int j = j0 + u * BLOCK;
+        if (j < v.np) {
+          v.lptr[j] = lp[u] - v.lbase;
           v.Fq[r[u]] = to_fixed((double)f[u] * inv_q);
           v.dH[r[u]] = 0.f;
           v.odeg[r[u]] = c1[u] - c0[u];
@@ -597,20 +601,23 @@ __device__ bool part_inflow(const PartArgs& a, const PartView& v, int p, const f
   const int e1 = a.ext_ptr[p + 1];
   constexpr int U = 8;  // eight gathers in flight per thread
   for (int e = a.ext_ptr[p] + skip * BLOCK + tid; e < e1; e += U * BLOCK) {
+    // every load unconditional (slots past the end repeat the last link and
+    // are dropped): a load under a per-lane branch must land before the
+    // branch joins, which would serialize the thread's eight gathers
     int32_t src[U];
     int r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool on = e + u * BLOCK < e1;
-      src[u] = on ? a.ext_src[e + u * BLOCK] : -1;
-      r[u] = on ? a.ext_row[e + u * BLOCK] : 0;
+      const int ee = min(e + u * BLOCK, e1 - 1);
+      src[u] = a.ext_src[ee];
+      r[u] = a.ext_row[ee];
     }
     float x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = src[u] >= 0 ? ld(src[u]) : 0.f;
+    for (int u = 0; u < U; ++u) x[u] = ld(src[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (x[u] != 0.f) add_fixed(&v.Fq[r[u]], to_fixed((double)x[u] * inv_q));
+      if (e + u * BLOCK < e1 && x[u] != 0.f) add_fixed(&v.Fq[r[u]], to_fixed((double)x[u] * inv_q));
   }
   bool ok = true;
   const int k1 = a.part_items[p + 1];
