@@ -91,10 +91,11 @@ typedef struct {
   int32_t block;       /* threads per workgroup (64..1024, multiple of 64); 0 = auto */
   int32_t wg_per_cu;   /* resident workgroups per CU for the persistent kernel; 0 = auto */
   int32_t sweeps_per_claim; /* ASYNC: local sweeps per partition claim when partitions
-                               outnumber workgroups; PARTITION: local sweeps per launch (m);
-                               0 = auto */
+                               outnumber workgroups; PARTITION: local sweeps per threshold
+                               level (m); 0 = auto (2) */
   int32_t max_rounds;  /* persistent launches (each followed by an exact residual) */
-  int32_t max_sweeps;  /* sweep budget per launch and workgroup (0 = auto) */
+  int32_t max_sweeps;  /* PARTITION: threshold levels per stage; ASYNC: sweeps per workgroup
+                          and launch; SWEEP: grid sweeps per stage (0 = auto) */
   int32_t xcd_remap;   /* 1: place neighbouring partitions on the same XCD */
   uint32_t flags;      /* DITR_FLAG_* bits */
 } ditr_opts;
