@@ -84,8 +84,10 @@ def _open(path):
     lib.dref_partition_uniform.argtypes = [i64, i64, vp]
     lib.dref_partition_cb.argtypes = [i64, vp, i64, vp]
     lib.dref_partition_cb_inout.argtypes = [i64, i64, vp, vp, i64, vp]
+    lib.dref_partition_mincut.argtypes = [i64, i64, vp, vp, i64, vp]
     for f in (lib.dref_check_csc, lib.dref_fluid_from_history, lib.dref_solve,
-              lib.dref_partition_uniform, lib.dref_partition_cb, lib.dref_partition_cb_inout):
+              lib.dref_partition_uniform, lib.dref_partition_cb, lib.dref_partition_cb_inout,
+              lib.dref_partition_mincut):
         f.restype = ctypes.c_int
     return lib
 
@@ -220,5 +222,16 @@ def partition_cb_inout(col_ptr, row_idx, K: int, lib=None) -> np.ndarray:
     ptr = np.empty(K + 1, np.int64)
     if _load(lib).dref_partition_cb_inout(col_ptr.size - 1, row_idx.size, col_ptr.ctypes.data,
                                           row_idx.ctypes.data, K, ptr.ctypes.data):
+        raise ValueError("bad partition count")
+    return ptr
+
+
+def partition_mincut(col_ptr, row_idx, K: int, lib=None) -> np.ndarray:
+    """CB boundaries moved, within windows and a 5% balance slack, to where the
+    fewest short links cross (least sum over the inner boundaries)."""
+    col_ptr, row_idx = _i32(col_ptr), _i32(row_idx)
+    ptr = np.empty(K + 1, np.int64)
+    if _load(lib).dref_partition_mincut(col_ptr.size - 1, row_idx.size, col_ptr.ctypes.data,
+                                        row_idx.ctypes.data, K, ptr.ctypes.data):
         raise ValueError("bad partition count")
     return ptr

@@ -356,3 +356,117 @@ int dref_partition_pmass(int64_t n, int64_t nnz, const int32_t* col_ptr, const i
   free(wout), free(in_ptr), free(in_src), free(win), free(fill);
   return DREF_OK;
 }
+
+/* Cut-minimizing cost-balanced partition: the CB boundaries slide, each within
+ * a window and under a balance slack, to where the fewest short links cross.
+ * It keeps more links inside their sets, the aim behind the internal-mass
+ * balance of Section 2.3, while the sets stay contiguous and balanced.
+ * Readings (the paper gives no rule; all of them are listed in the design
+ * notes):
+ *   - cost of node i: 1 + #out_i + min(#in_i, h) with h = max(1, floor(3L/N)):
+ *     a node's own work, its pushes, and its inflow up to h links (the inflow
+ *     of a row with more in-links is summed by all workgroups together);
+ *   - CB targets t_k: the smallest j with K C(j) >= k C(n), C the cost prefix;
+ *   - balance: every set costs at most cmax = cB + floor(cB / 10) and holds
+ *     at most smax = sB + floor(sB / 10) nodes, where cB and sB are the
+ *     largest cost and node count among the sets of the CB targets;
+ *   - a link i -> j (i != j) is short when |i - j| < 2 ceil(N/K); cross(b)
+ *     is the p mass of the short links with min(i, j) < b <= max(i, j), each
+ *     link weighing floor(p_ji 2^32) units, p_ji = d / #out_i with d = 0.85
+ *     (only the ratios matter: the weights rank positions, they move no fluid);
+ *   - boundary k moves within [t_k - w_k, t_k + w_k], w_k = min(ceil(N/K)/2,
+ *     half of each neighbouring target gap less one), so the windows are
+ *     disjoint and the CB targets stay feasible;
+ *   - the plan minimizes the sum of cross(b_k) over the inner boundaries;
+ *     among plans of equal sum, b_{K-1} is the smallest possible, then
+ *     b_{K-2}, and so on (a dynamic programme over the windows whose
+ *     back-pointers take the smallest of equal predecessors).
+ * ptr has K+1 entries. */
+int dref_partition_mincut(int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                          int64_t K, int64_t* ptr) {
+  if (K < 1 || K > (n > 0 ? n : 1)) return DREF_EINVAL;
+  int64_t* C = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  int64_t* indeg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  int64_t* cross = (int64_t*)calloc((size_t)n + 2, sizeof(int64_t));
+  int64_t* t = (int64_t*)calloc((size_t)K + 1, sizeof(int64_t));
+  int64_t* lo = (int64_t*)calloc((size_t)K + 1, sizeof(int64_t));
+  int64_t* hi = (int64_t*)calloc((size_t)K + 1, sizeof(int64_t));
+  int64_t* off = (int64_t*)calloc((size_t)K + 2, sizeof(int64_t));
+  if (!C || !indeg || !cross || !t || !lo || !hi || !off) {
+    free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+    return DREF_ENOMEM;
+  }
+  /* node costs and their prefix */
+  const int64_t h = nnz * 3 / (n > 0 ? n : 1) > 1 ? nnz * 3 / n : 1;
+  for (int64_t e = 0; e < nnz; ++e) indeg[row_idx[e]] += 1;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t out = col_ptr[i + 1] - col_ptr[i];
+    C[i + 1] = C[i] + 1 + out + (indeg[i] < h ? indeg[i] : h);
+  }
+  /* CB targets */
+  int64_t j = 0;
+  t[0] = 0;
+  for (int64_t k = 1; k < K; ++k) {
+    while (j < n && C[j] * K < k * C[n]) ++j;
+    t[k] = j;
+  }
+  t[K] = n;
+  /* balance limits */
+  int64_t cstar = 0, sstar = 0;
+  for (int64_t k = 0; k < K; ++k) {
+    if (C[t[k + 1]] - C[t[k]] > cstar) cstar = C[t[k + 1]] - C[t[k]];
+    if (t[k + 1] - t[k] > sstar) sstar = t[k + 1] - t[k];
+  }
+  const int64_t cmax = cstar + cstar / 10, smax = sstar + sstar / 10;
+  /* p mass of the short links crossing each position: cross[b] for b = 0..n */
+  const int64_t mean = (n + K - 1) / K, span = 2 * mean;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = col_ptr[i]; e < col_ptr[i + 1]; ++e) {
+      const int64_t r = row_idx[e];
+      const int64_t a = r < i ? r : i, z = r < i ? i : r;
+      if (a == z || z - a >= span) continue;
+      const int64_t u = link_units(NULL, 0.85, col_ptr, i, e);
+      for (int64_t b = a + 1; b <= z; ++b) cross[b] += u;
+    }
+  /* windows */
+  const int64_t W = mean / 2;
+  for (int64_t k = 1; k < K; ++k) {
+    int64_t w = W;
+    const int64_t gl = (t[k] - t[k - 1] - 1) / 2, gr = (t[k + 1] - t[k] - 1) / 2;
+    if (gl < w) w = gl;
+    if (gr < w) w = gr;
+    if (w < 0) w = 0;
+    lo[k] = t[k] - w;
+    hi[k] = t[k] + w;
+  }
+  lo[0] = hi[0] = 0;
+  lo[K] = hi[K] = n;
+  for (int64_t k = 0; k <= K; ++k) off[k + 1] = off[k] + (hi[k] - lo[k] + 1);
+  int64_t* V = (int64_t*)malloc(sizeof(int64_t) * (size_t)off[K + 1]);
+  int64_t* P = (int64_t*)malloc(sizeof(int64_t) * (size_t)off[K + 1]);
+  if (!V || !P) {
+    free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+    return DREF_ENOMEM;
+  }
+  const int64_t INF = INT64_MAX / 4;
+  V[0] = 0;
+  P[0] = -1;
+  /* V[k][b]: least sum of cross over boundaries 1..k with b_k = b */
+  for (int64_t k = 1; k <= K; ++k) {
+    for (int64_t b = lo[k]; b <= hi[k]; ++b) {
+      int64_t best = INF, arg = -1;
+      for (int64_t q = lo[k - 1]; q <= hi[k - 1]; ++q) {
+        const int64_t v = V[off[k - 1] + q - lo[k - 1]];
+        if (v >= INF || b - q > smax || C[b] - C[q] > cmax) continue;
+        if (v < best) best = v, arg = q;   /* strict: the smallest q among equals */
+      }
+      V[off[k] + b - lo[k]] = best >= INF ? INF : best + (k < K ? cross[b] : 0);
+      P[off[k] + b - lo[k]] = arg;
+    }
+  }
+  /* back from b_K = n (the CB targets are feasible, so V[K][n] is finite) */
+  ptr[K] = n;
+  for (int64_t k = K; k >= 1; --k) ptr[k - 1] = P[off[k] + ptr[k] - lo[k]];
+  free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+  return ptr[0] == 0 ? DREF_OK : DREF_EINVAL;
+}

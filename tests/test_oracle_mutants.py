@@ -53,6 +53,17 @@ MUTANTS = {
                                "if (in_src[q] >= a && in_src[q] <= j) inc += win[q];"),
     "pmass_first_fit_not_min_max": ("if (pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, mid, K, NULL) <= K) hi = mid;",
                                     "if (pmass_greedy(n, col_ptr, row_idx, wout, in_ptr, in_src, win, mid, K, NULL) <= K + 1) hi = mid;"),
+    # cut-minimizing partition
+    "mincut_tie_takes_last": ("if (v < best) best = v, arg = q;", "if (v <= best) best = v, arg = q;"),
+    "mincut_long_links_counted": ("if (a == z || z - a >= span) continue;", "if (a == z) continue;"),
+    "mincut_unweighted": ("const int64_t u = link_units(NULL, 0.85, col_ptr, i, e);", "const int64_t u = 1;"),
+    "mincut_in_cost_uncapped": ("C[i + 1] = C[i] + 1 + out + (indeg[i] < h ? indeg[i] : h);",
+                                "C[i + 1] = C[i] + 1 + out + indeg[i];"),
+    "mincut_no_slack": ("const int64_t cmax = cstar + cstar / 10, smax = sstar + sstar / 10;",
+                        "const int64_t cmax = cstar, smax = sstar;"),
+    "mincut_window_one_wider": ("lo[k] = t[k] - w;\n    hi[k] = t[k] + w;", "lo[k] = t[k] - w - 1;\n    hi[k] = t[k] + w + 1;"),
+    "mincut_crossing_off_by_one": ("for (int64_t b = a + 1; b <= z; ++b) cross[b] += u;",
+                                   "for (int64_t b = a; b < z; ++b) cross[b] += u;"),
 }
 
 
@@ -178,6 +189,43 @@ def general_pin_suite(lib):
         if max(masses) != tg.brute_min_max(scp, sri, w, K):
             fails.append("pmass_brute")
             break
+    import test_oracle_mincut as tm
+    cases = [(seed, n, K) for seed, n, K in [(0, 30, 2), (1, 30, 3), (3, 40, 4), (5, 25, 5), (6, 33, 3)]]
+    for seed, n, K in cases:
+        g = np.random.default_rng(seed)
+        mcp, mri = tm.local_graph(n, g, p_out=0.25 if seed % 2 else 0.5)
+        try:
+            got = oracle.partition_mincut(mcp, mri, K, lib=lib).tolist()
+        except ValueError:
+            got = None
+        if got != tm.brute_plan(mcp, mri, K)[0]:
+            fails.append("mincut_brute")
+            break
+    for seed, K in [(0, 3), (1, 4), (2, 3)]:
+        hcp, hri = tm.hub_graph(38, np.random.default_rng(50 + seed))
+        try:
+            got = oracle.partition_mincut(hcp, hri, K, lib=lib).tolist()
+        except ValueError:
+            got = None
+        if got != tm.brute_plan(hcp, hri, K)[0]:
+            fails.append("mincut_hubs")
+            break
+    for seed in (13, 17):
+        xcp, xri, K = tm.mixed_case(seed)
+        try:
+            got = oracle.partition_mincut(xcp, xri, K, lib=lib).tolist()
+        except ValueError:
+            got = None
+        if got != tm.brute_plan(xcp, xri, K)[0]:
+            fails.append("mincut_mixed")
+            break
+    ecp, eri = csc_from_edges(40, [])
+    try:
+        got = oracle.partition_mincut(ecp, eri, 4, lib=lib).tolist()
+    except ValueError:
+        got = None
+    if got != tm.brute_plan(ecp, eri, 4)[0]:
+        fails.append("mincut_ties")
     return fails
 
 
