@@ -60,9 +60,15 @@ enum { DITR_PART_CB = 0,       /* cost-balanced: contiguous ranges of ~L/K out-l
        DITR_PART_UNIFORM = 1,  /* contiguous ranges of floor(N/K) ids, last one takes the rest */
        DITR_PART_CB_INOUT = 2, /* contiguous ranges of ~2L/K in+out links: a partition's whole
                                   link cost (a cheap proxy for the balance below) */
-       DITR_PART_PMASS = 3     /* the alternative balance the paper proposes after the CB rule:
+       DITR_PART_PMASS = 3,    /* the alternative balance the paper proposes after the CB rule:
                                   equal internal p mass sum_{n,m in Omega_k} |p_nm| per block
-                                  (ditr_partition_pmass gives the exact rule) */ };
+                                  (ditr_partition_pmass gives the exact rule) */
+       DITR_PART_MINCUT = 4    /* cut-minimizing CB: CB targets on the node cost
+                                  1 + #out + min(#in, h), each boundary then moved within a
+                                  window, under a 10% balance slack, to where the least p mass
+                                  of short links crosses (keeps more of the p mass inside the
+                                  sets, the aim of the Section 2.3 alternative; exact rule at
+                                  ditr_partition) */ };
 
 /* Diffusion kernels. */
 enum { DITR_MODE_AUTO = 0,       /* = DITR_MODE_PARTITION */
@@ -236,7 +242,20 @@ int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, i
  * d_ptr (device int64, 1 <= K <= n). CB: omega_k = min { j : K col_ptr[j] >= k nnz }.
  * CB_INOUT: the same with col_ptr[j] + in_prefix[j] against 2 nnz, where
  * in_prefix counts the entries of d_row_idx below j (d_row_idx may be NULL for
- * the other types). Synchronizes for CB_INOUT (temporary in-link prefix). */
+ * CB and UNIFORM). MINCUT (reads d_row_idx):
+ *   - node cost c_i = 1 + #out_i + min(#in_i, h), h = max(1, floor(3 nnz / n)),
+ *     prefix C; targets t_k = min { j : K C(j) >= k C(n) };
+ *   - balance: every set costs at most cB + floor(cB/10) and holds at most
+ *     sB + floor(sB/10) nodes, cB and sB the largest over the targets' sets;
+ *   - a link i -> j, i != j, with |i - j| < 2 ceil(n/K) weighs
+ *     floor(0.85 / #out_i * 2^32); cross(b) sums those with min < b <= max;
+ *   - boundary k lies in [t_k - w_k, t_k + w_k], w_k = min(ceil(n/K)/2,
+ *     (t_k - t_{k-1} - 1)/2, (t_{k+1} - t_k - 1)/2), at least 0;
+ *   - the plan minimizes sum_k cross(b_k); among equal sums b_{K-1} is the
+ *     smallest possible, then b_{K-2}, and so on.
+ * Takes device temporaries of about 32 bytes per node; EINVAL if no plan is
+ * found (cannot happen for valid input: the targets are feasible).
+ * Synchronizes for CB_INOUT and MINCUT (temporary in-link prefix). */
 int ditr_partition(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
                    const int32_t* d_row_idx, int part_type, int64_t K, int64_t* d_ptr);
 /* Partition of equal internal p mass (Section 2.3, the balance the paper

@@ -426,8 +426,10 @@ int dref_partition_mincut(int64_t n, int64_t nnz, const int32_t* col_ptr, const 
       const int64_t a = r < i ? r : i, z = r < i ? i : r;
       if (a == z || z - a >= span) continue;
       const int64_t u = link_units(NULL, 0.85, col_ptr, i, e);
-      for (int64_t b = a + 1; b <= z; ++b) cross[b] += u;
+      cross[a + 1] += u; /* the link crosses b = a+1 .. z: a difference array */
+      cross[z + 1] -= u;
     }
+  for (int64_t b = 1; b <= n; ++b) cross[b] += cross[b - 1];
   /* windows */
   const int64_t W = mean / 2;
   for (int64_t k = 1; k < K; ++k) {

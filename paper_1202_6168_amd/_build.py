@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libditr.so")
-SOURCES = ["api.hip", "graph_k.hip", "solve_k.hip", "pull_k.hip", "part_k.hip", "batch_k.hip", "tune.hip", "gnn_k.hip", "noalloc.hip", "pmass_k.hip", "arena.hip", "adapt.hip"]
+SOURCES = ["api.hip", "graph_k.hip", "solve_k.hip", "pull_k.hip", "part_k.hip", "batch_k.hip", "tune.hip", "gnn_k.hip", "noalloc.hip", "pmass_k.hip", "mincut_k.hip", "arena.hip", "adapt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only. Packed FP32 instructions are switched off (-packed-fp32-ops);

@@ -164,17 +164,22 @@ int ditr_partition(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr
   if (n < 1 || K < 1 || K > n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
   if (part_type == DITR_PART_PMASS)
     return set_error(DITR_EINVAL, "the internal-mass partition needs the weights: use ditr_partition_pmass");
-  if (part_type != DITR_PART_CB && part_type != DITR_PART_UNIFORM && part_type != DITR_PART_CB_INOUT)
+  if (part_type != DITR_PART_CB && part_type != DITR_PART_UNIFORM && part_type != DITR_PART_CB_INOUT &&
+      part_type != DITR_PART_MINCUT)
     return set_error(DITR_EINVAL, "unknown partition type %d", part_type);
-  if (part_type == DITR_PART_CB_INOUT && nnz > 0 && !d_row_idx)
-    return set_error(DITR_EINVAL, "CB_INOUT needs the row indices");
+  if ((part_type == DITR_PART_CB_INOUT || part_type == DITR_PART_MINCUT) && nnz > 0 && !d_row_idx)
+    return set_error(DITR_EINVAL, "this partition type needs the row indices");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 31)) return set_error(DITR_EINVAL, "nnz out of range");
   HIP_TRY(hipSetDevice(c->device));
-  if (part_type != DITR_PART_CB_INOUT)
+  if (part_type != DITR_PART_CB_INOUT && part_type != DITR_PART_MINCUT)
     return launch_partition(c, n, d_col_ptr, nullptr, part_type, K, d_ptr, nullptr);
   int32_t* in_prefix = nullptr;
   HIP_TRY(hipMalloc((void**)&in_prefix, sizeof(int32_t) * (n + 1)));
   int rc = launch_in_prefix(c, n, nnz, d_row_idx, in_prefix);
-  if (!rc) rc = launch_partition(c, n, d_col_ptr, in_prefix, part_type, K, d_ptr, nullptr);
+  if (!rc)
+    rc = part_type == DITR_PART_MINCUT
+             ? launch_partition_mincut(c, n, nnz, d_col_ptr, d_row_idx, in_prefix, K, d_ptr, nullptr)
+             : launch_partition(c, n, d_col_ptr, in_prefix, part_type, K, d_ptr, nullptr);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(in_prefix);
   return rc;
@@ -229,6 +234,9 @@ static int make_plan(ditr_ctx* c, ditr_graph* g, int64_t K) {
   int rc = g->part_type == DITR_PART_PMASS
                ? launch_partition_pmass(c, g->n, g->nnz, g->col_ptr, g->row_idx, g->val, g->d, K, tmp,
                                         g->part_ptr, g)
+           : g->part_type == DITR_PART_MINCUT
+               ? launch_partition_mincut(c, g->n, g->nnz, g->col_ptr, g->row_idx, g->row_ptr, K, tmp,
+                                         g->part_ptr, g)
                : launch_partition(c, g->n, g->col_ptr, g->row_ptr, g->part_type, K, tmp, g->part_ptr);
   hipError_t e = rc ? hipSuccess
                     : hipMemcpyAsync(g->part_ptr_host, tmp, sizeof(int64_t) * (K + 1),
@@ -302,7 +310,7 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
   ditr_opts_default(&o);
   if (opts) o = *opts;
   if (o.part_type != DITR_PART_CB && o.part_type != DITR_PART_UNIFORM &&
-      o.part_type != DITR_PART_CB_INOUT && o.part_type != DITR_PART_PMASS)
+      o.part_type != DITR_PART_CB_INOUT && o.part_type != DITR_PART_PMASS && o.part_type != DITR_PART_MINCUT)
     return set_error(DITR_EINVAL, "unknown partition type %d", o.part_type);
   if (o.block == 0) o.block = 1024;
   if (o.block != 256 && o.block != 512 && o.block != 1024)

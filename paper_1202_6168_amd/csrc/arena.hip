@@ -68,6 +68,7 @@ size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part
   // one partition plan (each retry reuses the same space)
   b += al(4 * (K + 1)) + al(8 * K) + al(4 * K) + al(8 * (K + 1));
   if (part_type == DITR_PART_PMASS) b += pmass_temp_bytes(n, nnz);
+  if (part_type == DITR_PART_MINCUT) b += mincut_temp_bytes(n, (int64_t)K);
   // the partitioned-sweep tables and the temporaries of their build (left in
   // place in a workspace): ids, local CSC, external links, heavy rows, items
   // and their work units, the two sorts, six scans

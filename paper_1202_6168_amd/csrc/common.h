@@ -276,6 +276,10 @@ int launch_partition_pmass(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* c
                            const int32_t* row_idx, const double* val, double d, int64_t K,
                            int64_t* out64, int32_t* out32, ditr_graph* g = nullptr);
 size_t pmass_temp_bytes(int64_t n, int64_t nnz);
+int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                            const int32_t* in_ptr, int64_t K, int64_t* out64, int32_t* out32,
+                            ditr_graph* g = nullptr);
+size_t mincut_temp_bytes(int64_t n, int64_t K);
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);

@@ -1,0 +1,342 @@
+// Cut-minimizing cost-balanced partition. Section 2.3 chooses the sets so
+// that the work balances (CB) and proposes sets that keep more of the p mass
+// inside them; this plan does both: it starts from CB targets and slides each
+// inner boundary, within a window and a balance slack, to where the least p
+// mass of short links crosses.
+//
+// Definition (the oracle's, step for step):
+//   * node cost 1 + #out_i + min(#in_i, h), h = max(1, floor(3 L / N)): its own
+//     work, its pushes, and its inflow up to h links (a row with more in-links
+//     has them summed by all workgroups together); C is the cost prefix;
+//   * targets t_k = min { j : K C(j) >= k C(N) };
+//   * every set costs at most cB + cB / 10 and holds at most sB + sB / 10 nodes,
+//     cB and sB the largest among the sets of the targets;
+//   * a link i -> j (i != j) is short when |i - j| < 2 ceil(N/K) (a longer link
+//     crosses some boundary wherever the boundaries sit) and weighs
+//     floor(0.85 / #out_i 2^32) units; cross(b) sums the short links with
+//     min(i, j) < b <= max(i, j);
+//   * boundary k lies in [t_k - w_k, t_k + w_k], w_k = min(ceil(N/K) / 2, half
+//     of each neighbouring target gap less one): the windows are disjoint and
+//     the targets themselves are a feasible plan;
+//   * the plan minimizes the sum of cross(b_k); among equal sums the last
+//     boundary is the smallest possible, then the one before, and so on.
+//
+// Device plan: the costs and their scan, the targets by binary search, the
+// crossing mass as a difference array (two atomics per short link, one per
+// column for the end at the column's own id) and its scan, then a dynamic
+// programme in one workgroup, one window per step: a suffix minimum (value,
+// position) of the previous window, and each position of the current window
+// takes the best predecessor its balance limits admit (a binary search on
+// C). Back-pointers hold the smallest predecessor among equals.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kMcBlock = 1024;
+constexpr long long kMcInf = 0x7fffffffffffffffLL / 4;
+
+int mc_grid(int64_t items, int block, int64_t cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((items + block - 1) / block, cap));
+}
+
+__global__ void k_mc_cost(int64_t n, const int32_t* __restrict__ col_ptr, const int32_t* __restrict__ in_ptr,
+                          long long h, long long* c) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += stride) {
+    if (i == n) {
+      c[n] = 0;
+      continue;
+    }
+    const long long in = (long long)in_ptr[i + 1] - in_ptr[i];
+    c[i] = 1 + ((long long)col_ptr[i + 1] - col_ptr[i]) + (in < h ? in : h);
+  }
+}
+
+__global__ void k_mc_targets(int64_t n, int64_t K, const long long* __restrict__ C, long long* t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const long long total = C[n];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k <= K; k += stride) {
+    long long w;
+    if (k == 0) w = 0;
+    else if (k == K) w = n;
+    else {
+      int64_t lo = 0, hi = n;  // first j with K C(j) >= k C(n), in [lo, hi]
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (C[mid] * K >= k * total) hi = mid; else lo = mid + 1;
+      }
+      w = lo;
+    }
+    t[k] = w;
+  }
+}
+
+// lim[0] = largest set cost, lim[1] = largest set size of the targets
+__global__ void k_mc_limits(int64_t K, const long long* __restrict__ C, const long long* __restrict__ t,
+                            unsigned long long* lim) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < K; k += stride) {
+    atomicMax(&lim[0], (unsigned long long)(C[t[k + 1]] - C[t[k]]));
+    atomicMax(&lim[1], (unsigned long long)(t[k + 1] - t[k]));
+  }
+}
+
+// windows [lo_k, hi_k] and their sizes (size[K + 1] = 0 closes the scan)
+__global__ void k_mc_windows(int64_t n, int64_t K, long long W, const long long* __restrict__ t, long long* lo,
+                             long long* hi, long long* size) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k <= K + 1; k += stride) {
+    if (k == K + 1) {
+      size[k] = 0;
+      continue;
+    }
+    long long a, z;
+    if (k == 0) a = z = 0;
+    else if (k == K) a = z = n;
+    else {
+      long long w = W;
+      const long long gl = (t[k] - t[k - 1] - 1) / 2, gr = (t[k + 1] - t[k] - 1) / 2;
+      w = gl < w ? gl : w;
+      w = gr < w ? gr : w;
+      w = w < 0 ? 0 : w;
+      a = t[k] - w;
+      z = t[k] + w;
+    }
+    lo[k] = a;
+    hi[k] = z;
+    size[k] = z - a + 1;
+  }
+}
+
+// difference array of the crossing mass: diff[a + 1] += u, diff[z + 1] -= u
+// for each short link between a < z (modulo 2^64; the scan gives the true
+// nonnegative sums)
+__global__ void k_mc_cross(int64_t n, long long span, const int32_t* __restrict__ col_ptr,
+                           const int32_t* __restrict__ row_idx, unsigned long long* diff) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int32_t e0 = col_ptr[i], e1 = col_ptr[i + 1];
+    if (e1 == e0) continue;
+    const unsigned long long u = (unsigned long long)floor(0.85 / (double)(e1 - e0) * 4294967296.0);
+    unsigned long long own = 0;  // net change at diff[i + 1]
+    for (int32_t e = e0; e < e1; ++e) {
+      const int64_t r = row_idx[e];
+      if (r == i) continue;
+      if (r > i) {
+        if (r - i >= span) continue;
+        own += u;
+        atomicAdd(&diff[r + 1], (unsigned long long)0 - u);
+      } else {
+        if (i - r >= span) continue;
+        own -= u;
+        atomicAdd(&diff[r + 1], u);
+      }
+    }
+    if (own) atomicAdd(&diff[i + 1], own);
+  }
+}
+
+// The dynamic programme (one workgroup). Va/Vb: values of the previous and
+// the current window; smv/smi: suffix minimum of the previous window (value,
+// position); back: the chosen predecessor of every window position, at
+// off[k] + (b - lo[k]).
+__global__ void __launch_bounds__(kMcBlock) k_mc_dp(int64_t n, int64_t K, const long long* __restrict__ C,
+                                                  const unsigned long long* __restrict__ cross,
+                                                  const long long* __restrict__ lo, const long long* __restrict__ hi,
+                                                  const long long* __restrict__ off, long long cmax, long long smax,
+                                                  long long* Va, long long* Vb, long long* smv, int32_t* smi,
+                                                  int32_t* back, int64_t* out64, int32_t* out32, int* err) {
+  __shared__ long long s_val[kMcBlock];
+  __shared__ int32_t s_pos[kMcBlock];
+  const int tid = threadIdx.x;
+  long long* Vp = Va;
+  long long* Vc = Vb;
+  if (tid == 0) Vp[0] = 0;  // window 0 is {0}
+  __syncthreads();
+  for (int64_t k = 1; k <= K; ++k) {
+    const long long plo = lo[k - 1], pm = hi[k - 1] - plo + 1;
+    // suffix minimum of the previous window: each thread a chunk, from its
+    // right end (a smaller position wins a tie), then across the chunks
+    const long long ch = (pm + kMcBlock - 1) / kMcBlock;
+    const long long c0 = (long long)tid * ch, c1 = c0 + ch < pm ? c0 + ch : pm;
+    long long bv = kMcInf;
+    int32_t bp = -1;
+    for (long long i = c1 - 1; i >= c0; --i) {
+      const long long v = Vp[i];
+      if (v <= bv) {
+        bv = v;
+        bp = (int32_t)(plo + i);
+      }
+      smv[i] = bv;
+      smi[i] = bp;
+    }
+    s_val[tid] = bv;
+    s_pos[tid] = bp;
+    __syncthreads();
+    for (int d = 1; d < kMcBlock; d <<= 1) {
+      long long ov = kMcInf;
+      int32_t op = -1;
+      if (tid + d < kMcBlock) {
+        ov = s_val[tid + d];
+        op = s_pos[tid + d];
+      }
+      __syncthreads();
+      if (ov < s_val[tid]) {  // strict: the left (smaller positions) keeps a tie
+        s_val[tid] = ov;
+        s_pos[tid] = op;
+      }
+      __syncthreads();
+    }
+    const long long rv = tid + 1 < kMcBlock ? s_val[tid + 1] : kMcInf;
+    const int32_t rp = tid + 1 < kMcBlock ? s_pos[tid + 1] : -1;
+    for (long long i = c0; i < c1; ++i)
+      if (rv < smv[i]) {
+        smv[i] = rv;
+        smi[i] = rp;
+      }
+    __syncthreads();
+    // the current window: each position's best admissible predecessor
+    const long long clo = lo[k], cm = hi[k] - clo + 1, phi = hi[k - 1];
+    for (long long j = tid; j < cm; j += kMcBlock) {
+      const long long b = clo + j;
+      long long a = b - smax > plo ? b - smax : plo, z = phi + 1;
+      const long long need = C[b] - cmax;  // first q in [a, phi] with C(q) >= C(b) - cmax
+      while (a < z) {
+        const long long mid = (a + z) >> 1;
+        if (C[mid] < need) a = mid + 1; else z = mid;
+      }
+      long long v = kMcInf;
+      int32_t p = -1;
+      if (a <= phi) {
+        v = smv[a - plo];
+        p = smi[a - plo];
+      }
+      Vc[j] = v >= kMcInf ? kMcInf : v + (k < K ? (long long)cross[b] : 0);
+      back[off[k] + j] = v >= kMcInf ? -1 : p;
+    }
+    __syncthreads();
+    long long* tmp = Vp;
+    Vp = Vc;
+    Vc = tmp;
+  }
+  if (tid == 0) {
+    long long b = n;
+    if (out64) out64[K] = n;
+    if (out32) out32[K] = (int32_t)n;
+    for (int64_t k = K; k >= 1; --k) {
+      const int32_t q = back[off[k] + (b - lo[k])];
+      if (q < 0) {
+        *err = 1;
+        return;
+      }
+      b = q;
+      if (out64) out64[k - 1] = b;
+      if (out32) out32[k - 1] = (int32_t)b;
+    }
+    if (b != 0) *err = 1;
+  }
+}
+
+struct McSizes {
+  size_t scan_n = 0, scan_k = 0, scan_x = 0;
+};
+
+McSizes mc_scan_sizes(int64_t n, int64_t K) {
+  McSizes s;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s.scan_n, (long long*)nullptr, (long long*)nullptr, (int)(n + 1));
+  (void)hipcub::DeviceScan::InclusiveSum(nullptr, s.scan_x, (unsigned long long*)nullptr,
+                                         (unsigned long long*)nullptr, (int)(n + 1));
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s.scan_k, (long long*)nullptr, (long long*)nullptr, (int)(K + 2));
+  return s;
+}
+
+}  // namespace
+
+// K+1 boundaries of the cut-minimizing partition into out64 and/or out32
+// (device). in_ptr: the in-link prefix (CSR row pointer). Synchronizes.
+int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
+                            const int32_t* in_ptr, int64_t K, int64_t* out64, int32_t* out32, ditr_graph* g) {
+  hipStream_t st = c->stream;
+  std::vector<void*> owned;
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    bytes = std::max<size_t>(bytes, 16);
+    if ((g ? g_alloc(g, p, bytes) : hipMalloc(p, bytes)) != hipSuccess) return false;
+    owned.push_back(*p);
+    return true;
+  };
+  auto done = [&](int rc) {
+    (void)hipStreamSynchronize(st);
+    for (void* p : owned) {
+      if (g) g_free(g, p);
+      else (void)hipFree(p);
+    }
+    return rc;
+  };
+  if (n < 1 || K < 1 || K > n) return set_error(DITR_EINVAL, "need 1 <= K <= n");
+  const long long h = std::max<long long>(1, 3 * (long long)nnz / n);
+  const long long mean = (n + K - 1) / K, span = 2 * mean, W = mean / 2;
+  const size_t win = (size_t)(2 * W + 2);
+  const size_t nback = (size_t)(K + 1) * (size_t)(2 * W + 1);
+  const McSizes ss = mc_scan_sizes(n, K);
+  long long *cst, *C, *t, *lo, *hi, *size, *off, *Va, *Vb, *smv;
+  unsigned long long *cross, *lim;
+  int32_t *smi, *back;
+  int* err;
+  void *tn, *tk, *tx;
+  if (!alloc((void**)&cst, 8 * (n + 1)) || !alloc((void**)&C, 8 * (n + 1)) || !alloc((void**)&cross, 8 * (n + 1)) ||
+      !alloc((void**)&t, 8 * (K + 1)) || !alloc((void**)&lo, 8 * (K + 1)) || !alloc((void**)&hi, 8 * (K + 1)) ||
+      !alloc((void**)&size, 8 * (K + 2)) || !alloc((void**)&off, 8 * (K + 2)) || !alloc((void**)&lim, 16) ||
+      !alloc((void**)&Va, 8 * win) || !alloc((void**)&Vb, 8 * win) || !alloc((void**)&smv, 8 * win) ||
+      !alloc((void**)&smi, 4 * win) || !alloc((void**)&back, 4 * nback) || !alloc((void**)&err, 4) ||
+      !alloc(&tn, ss.scan_n) || !alloc(&tk, ss.scan_k) || !alloc(&tx, ss.scan_x))
+    return done(set_error(DITR_ENOMEM, "device allocation failed (cut-minimizing partition)"));
+  size_t bn = ss.scan_n, bk = ss.scan_k, bx = ss.scan_x;
+  // costs, their prefix, the targets, the balance limits and the windows
+  k_mc_cost<<<mc_grid(n + 1, 256, 16384), 256, 0, st>>>(n, col_ptr, in_ptr, h, cst);
+  if (hipcub::DeviceScan::ExclusiveSum(tn, bn, cst, C, (int)(n + 1), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "cost scan failed"));
+  k_mc_targets<<<mc_grid(K + 1, 256, 4096), 256, 0, st>>>(n, K, C, t);
+  if (hipMemsetAsync(lim, 0, 16, st) != hipSuccess || hipMemsetAsync(err, 0, 4, st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "hipMemsetAsync failed"));
+  k_mc_limits<<<mc_grid(K, 256, 4096), 256, 0, st>>>(K, C, t, lim);
+  k_mc_windows<<<mc_grid(K + 2, 256, 4096), 256, 0, st>>>(n, K, W, t, lo, hi, size);
+  if (hipcub::DeviceScan::ExclusiveSum(tk, bk, size, off, (int)(K + 2), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "window scan failed"));
+  // crossing mass of every position (cst is reused as the difference array)
+  unsigned long long* diff = reinterpret_cast<unsigned long long*>(cst);
+  if (hipMemsetAsync(diff, 0, 8 * (n + 1), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "hipMemsetAsync failed"));
+  if (nnz > 0) k_mc_cross<<<mc_grid(n, 256, 16384), 256, 0, st>>>(n, span, col_ptr, row_idx, diff);
+  if (hipcub::DeviceScan::InclusiveSum(tx, bx, diff, cross, (int)(n + 1), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "crossing scan failed"));
+  unsigned long long hl[2] = {0, 0};
+  if (hipGetLastError() != hipSuccess || hipMemcpyAsync(hl, lim, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "cut-minimizing partition setup failed"));
+  const long long cmax = (long long)hl[0] + (long long)hl[0] / 10, smax = (long long)hl[1] + (long long)hl[1] / 10;
+  k_mc_dp<<<1, kMcBlock, 0, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, Va, Vb, smv, smi, back, out64, out32,
+                                  err);
+  int herr = 0;
+  if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "cut-minimizing partition failed"));
+  if (herr) return done(set_error(DITR_EINVAL, "cut-minimizing partition found no plan"));
+  return done(DITR_OK);
+}
+
+// device bytes launch_partition_mincut takes for its temporaries (an upper
+// bound, with the scans' own scratch)
+size_t mincut_temp_bytes(int64_t n, int64_t K) {
+  auto al = [](size_t x) { return (std::max<size_t>(x, 16) + 255) & ~(size_t)255; };
+  const McSizes ss = mc_scan_sizes(n, K);
+  const size_t N = (size_t)n, KK = (size_t)std::max<int64_t>(K, 1);
+  const size_t W = ((N + KK - 1) / KK) / 2;
+  return 3 * al(8 * (N + 1)) + 3 * al(8 * (KK + 1)) + 2 * al(8 * (KK + 2)) + al(16) + 3 * al(8 * (2 * W + 2)) +
+         al(4 * (2 * W + 2)) + al(4 * (KK + 1) * (2 * W + 1)) + al(4) + al(ss.scan_n) + al(ss.scan_k) +
+         al(ss.scan_x) + 4096;
+}

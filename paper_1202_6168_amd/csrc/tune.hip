@@ -253,7 +253,8 @@ bool read_cache(const char* path, std::vector<Entry>& out) {
     en.default_seconds = num("default_seconds", 0);
     if (!(en.alpha > 1) || !(en.refresh_at >= 0) || en.part_nodes < 0 || en.m < 0 ||
         (en.part_type != DITR_PART_CB && en.part_type != DITR_PART_UNIFORM &&
-         en.part_type != DITR_PART_CB_INOUT && en.part_type != DITR_PART_PMASS))
+         en.part_type != DITR_PART_CB_INOUT && en.part_type != DITR_PART_PMASS &&
+         en.part_type != DITR_PART_MINCUT))
       continue;
     out.push_back(en);
   }
@@ -360,7 +361,8 @@ int ditr_tune_cache_put(const char* path, uint64_t key, const ditr_opts* o, doub
   if (!path || !o) return set_error(DITR_EINVAL, "NULL argument");
   if (!(o->alpha > 1) || !(o->refresh_at >= 0) || o->part_nodes < 0 || o->sweeps_per_claim < 0 ||
       (o->part_type != DITR_PART_CB && o->part_type != DITR_PART_UNIFORM &&
-       o->part_type != DITR_PART_CB_INOUT && o->part_type != DITR_PART_PMASS))
+       o->part_type != DITR_PART_CB_INOUT && o->part_type != DITR_PART_PMASS &&
+       o->part_type != DITR_PART_MINCUT))
     return set_error(DITR_EINVAL, "options out of range");
   Entry e;
   e.key = key;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libditr.so")
 
 OK, NOT_CONVERGED, ABORTED, NOT_FOUND = 0, 1, 2, 3
 EINVAL, EGRAPH, ENOMEM, EHIP, ENONFINITE = -1, -2, -3, -4, -5
-PART_CB, PART_UNIFORM, PART_CB_INOUT, PART_PMASS = 0, 1, 2, 3
+PART_CB, PART_UNIFORM, PART_CB_INOUT, PART_PMASS, PART_MINCUT = 0, 1, 2, 3, 4
 MODE_AUTO, MODE_ASYNC, MODE_SWEEP, MODE_PARTITION = 0, 1, 2, 3
 FLAG_TIME_KERNELS = 1
 FLAG_NO_RESIDENT = 2

@@ -36,7 +36,7 @@ def _problem(n, seed, block=1000):
     return cp, ri, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)
 
 
-@pytest.mark.parametrize("part_type", [ditr.PART_CB_INOUT, ditr.PART_PMASS])
+@pytest.mark.parametrize("part_type", [ditr.PART_CB_INOUT, ditr.PART_PMASS, ditr.PART_MINCUT])
 def test_upload_into_workspace_and_solve(ctx, part_type):
     cp, ri, cpt, rit = _problem(60_000, 41)
     n, nnz = cp.size - 1, ri.size

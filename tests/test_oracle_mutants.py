@@ -62,8 +62,8 @@ MUTANTS = {
     "mincut_no_slack": ("const int64_t cmax = cstar + cstar / 10, smax = sstar + sstar / 10;",
                         "const int64_t cmax = cstar, smax = sstar;"),
     "mincut_window_one_wider": ("lo[k] = t[k] - w;\n    hi[k] = t[k] + w;", "lo[k] = t[k] - w - 1;\n    hi[k] = t[k] + w + 1;"),
-    "mincut_crossing_off_by_one": ("for (int64_t b = a + 1; b <= z; ++b) cross[b] += u;",
-                                   "for (int64_t b = a; b < z; ++b) cross[b] += u;"),
+    "mincut_crossing_off_by_one": ("cross[a + 1] += u; /* the link", "cross[a] += u; /* the link"),
+    "mincut_crossing_end_kept": ("      cross[z + 1] -= u;\n", "      cross[z] -= u;\n"),
 }
 
 
