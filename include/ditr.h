@@ -83,7 +83,7 @@ enum { DITR_MODE_AUTO = 0,       /* = DITR_MODE_PARTITION */
                                     resident across levels when they all fit the device */ };
 
 typedef struct {
-  double alpha;        /* threshold divisor after each sweep (Section 2.4); > 1; default 1.5 */
+  double alpha;        /* threshold divisor after each sweep (Section 2.4); > 1; default 2 */
   double refresh_at;   /* first exact FP64 residual refresh once ||F||_1 <= refresh_at ||B||_1
                           (cancels FP32 rounding drift); >= 0; default 0, the library's
                           choice: 1e-7 (partitioned and pull sweeps), 1e-5 (asynchronous
@@ -92,13 +92,13 @@ typedef struct {
                           node share of the remaining fluid (Section 2.4, r_k < T); default 0.5 */
   double rescale_cap;  /* max factor a reception may raise a partition threshold (Section 2.6) */
   int32_t mode;        /* DITR_MODE_* */
-  int32_t part_type;   /* DITR_PART_* */
+  int32_t part_type;   /* DITR_PART_*; default DITR_PART_MINCUT */
   int32_t part_nodes;  /* nodes per partition target; 0 = from LDS capacity */
   int32_t block;       /* threads per workgroup (64..1024, multiple of 64); 0 = auto */
   int32_t wg_per_cu;   /* resident workgroups per CU for the persistent kernel; 0 = auto */
   int32_t sweeps_per_claim; /* ASYNC: local sweeps per partition claim when partitions
                                outnumber workgroups; PARTITION: local sweeps per threshold
-                               level (m); 0 = auto (2) */
+                               level (m); 0 = auto (2 for ASYNC, 3 for PARTITION) */
   int32_t max_rounds;  /* persistent launches (each followed by an exact residual) */
   int32_t max_sweeps;  /* PARTITION: threshold levels per stage; ASYNC: sweeps per workgroup
                           and launch; SWEEP: grid sweeps per stage (0 = auto) */

@@ -58,12 +58,12 @@ const char* ditr_last_error(void) { return g_err; }
 int ditr_opts_default(ditr_opts* o) {
   if (!o) return set_error(DITR_EINVAL, "opts is NULL");
   memset(o, 0, sizeof(*o));
-  o->alpha = 1.5;
+  o->alpha = 2.0;
   o->refresh_at = 0;  // the library's choice for the mode
   o->park_ratio = 0.5;
   o->rescale_cap = 4.0;
   o->mode = DITR_MODE_AUTO;
-  o->part_type = DITR_PART_CB_INOUT;
+  o->part_type = DITR_PART_MINCUT;
   o->part_nodes = 0;
   o->block = 1024;
   o->wg_per_cu = 1;
@@ -735,7 +735,7 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
                                      : launch_set_launch_target(c, r, stage, T0);
     if (rc) return finish(rc);
     if (mode == DITR_MODE_PARTITION) {
-      const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 2;
+      const int m = o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 3;
       const int batch = kBatch;
       const int64_t budget = o.max_sweeps > 0 ? o.max_sweeps : 4096;
       bool resident = false;

@@ -4,10 +4,13 @@
 // problem and cached in a JSON file keyed by a fingerprint of that problem.
 //
 // The paper finds alpha uninfluential over [1.2, 2] (Section 2.4) and the
-// partition balance decisive (Section 3.2), so the search is a short
-// coordinate descent: partition first, then alpha, local sweeps and the
-// refresh point, each candidate accepted only when it beats the incumbent by
-// a margin larger than the timing noise.
+// partition balance decisive (Section 3.2). On the GPU each threshold level
+// costs about the same whatever it diffuses, so a larger alpha (fewer levels)
+// can pay once the plan keeps the levels from being bound by the exchange:
+// the alpha grid reaches 3. The search is a short coordinate descent:
+// partition first, then alpha, local sweeps and the refresh point, each
+// candidate accepted only when it beats the incumbent by a margin larger
+// than the timing noise.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -208,8 +211,8 @@ struct JParser {
 //         "part_nodes": .., "sweeps_per_claim": .., "seconds": .., "default_seconds": ..}
 struct Entry {
   uint64_t key = 0;
-  double alpha = 1.5, refresh_at = 0;
-  int part_type = DITR_PART_CB_INOUT, part_nodes = 0, m = 0;
+  double alpha = 2.0, refresh_at = 0;
+  int part_type = DITR_PART_MINCUT, part_nodes = 0, m = 0;
   double seconds = 0, default_seconds = 0;
 };
 
@@ -244,9 +247,9 @@ bool read_cache(const char* path, std::vector<Entry>& out) {
       const JVal* v = e.get(name);
       return v && v->kind == JVal::NUM ? v->num : dflt;
     };
-    en.alpha = num("alpha", 1.5);
+    en.alpha = num("alpha", 2.0);
     en.refresh_at = num("refresh_at", 0);
-    en.part_type = (int)num("part_type", DITR_PART_CB_INOUT);
+    en.part_type = (int)num("part_type", DITR_PART_MINCUT);
     en.part_nodes = (int)num("part_nodes", 0);
     en.m = (int)num("sweeps_per_claim", 0);
     en.seconds = num("seconds", 0);
@@ -471,8 +474,9 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
   };
 
   // stage 1: partition plan (type x nodes per partition; 0 = the library's choice)
-  const int types_all[4] = {DITR_PART_CB_INOUT, DITR_PART_CB, DITR_PART_UNIFORM, DITR_PART_PMASS};
-  const int ntypes = effort == 0 ? 1 : 4;
+  const int types_all[5] = {DITR_PART_MINCUT, DITR_PART_CB_INOUT, DITR_PART_CB, DITR_PART_UNIFORM,
+                            DITR_PART_PMASS};
+  const int ntypes = effort == 0 ? 1 : 5;
   const int sizes[6] = {0, 1024, 2048, 3072, 6144, 8192};
   for (int ti = 0; ti < ntypes; ++ti)
     for (int s : sizes) {
@@ -484,8 +488,8 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
     }
   const int passes = effort == 2 ? 2 : 1;
   for (int pass = 0; pass < passes; ++pass) {
-    // stage 2: threshold divisor alpha (Section 2.4: [1.2, 2])
-    for (double a : {1.2, 1.35, 1.5, 1.75, 2.0}) {
+    // stage 2: threshold divisor alpha (Section 2.4: [1.2, 2], and beyond)
+    for (double a : {1.2, 1.5, 1.75, 2.0, 2.5, 3.0}) {
       Entry e = best;
       e.alpha = a;
       if (a == best.alpha) continue;
@@ -496,7 +500,7 @@ int ditr_tune(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
     for (int m : {1, 2, 3, 4}) {
       Entry e = best;
       e.m = m;
-      if (m == (best.m > 0 ? best.m : 2)) continue;
+      if (m == (best.m > 0 ? best.m : 3)) continue;
       if ((rc = consider(e))) return rc;
     }
     // stage 4: first exact refresh

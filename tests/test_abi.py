@@ -37,7 +37,7 @@ def test_binding_covers_every_declared_symbol():
 def test_version_and_defaults():
     assert ditr.version() == 1
     o = ditr.opts_default()
-    assert o.alpha == 1.5 and o.refresh_at == 0 and o.part_type == ditr.PART_CB_INOUT
+    assert o.alpha == 2.0 and o.refresh_at == 0 and o.part_type == ditr.PART_MINCUT
     with pytest.raises(KeyError):
         ditr.opts_default(no_such_field=1)
 

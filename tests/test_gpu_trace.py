@@ -85,10 +85,14 @@ def test_trace_accounts_for_the_solve(ctx, problem, flags):
     else:
         assert st.idle_polls >= 0
     # nonnegative fluid: the exact residual after the last level is its held
-    # plus in-flight fluid (up to the rounding of the last stage's moved fluid)
+    # plus in-flight fluid, up to the rounding of the last stage's moved fluid.
+    # The relaunched levels also store every F_i in FP32 between levels (2^-24
+    # of the fluid of the early levels of the stage, some 1e5 times the final
+    # residual), the resident kernel keeps it in LDS in fixed point.
     last = written[(L - 1) * K:L * K]
     tracked = last[:, 0].sum() + last[:, 1].sum()
-    assert abs(tracked - st.resid_l1) <= 1e-4 * st.resid_l1 + 1e-13 * b1, (tracked, st.resid_l1)
+    rel = 2e-3 if flags & ditr.FLAG_NO_RESIDENT else 1e-4
+    assert abs(tracked - st.resid_l1) <= rel * st.resid_l1 + 1e-13 * b1, (tracked, st.resid_l1)
 
 
 def test_trace_capacity_is_respected(ctx, problem):

@@ -44,7 +44,8 @@ def test_tune_search_cache_and_parity(ctx, problem, tmp_path):
     assert info.from_cache == 0 and info.candidates >= 15
     assert 0 < info.best_seconds <= info.default_seconds
     assert info.best_edges > 0 and info.default_edges > 0
-    assert 1.2 <= o.alpha <= 2.0 and o.part_type in (ditr.PART_CB, ditr.PART_UNIFORM, ditr.PART_CB_INOUT, ditr.PART_PMASS)
+    assert 1.2 <= o.alpha <= 3.0 and o.part_type in (ditr.PART_CB, ditr.PART_UNIFORM, ditr.PART_CB_INOUT,
+                                                   ditr.PART_PMASS, ditr.PART_MINCUT)
     doc = json.load(open(cache))
     assert [e["key"] for e in doc["entries"]] == ["%016x" % info.key]
 
