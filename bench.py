@@ -72,6 +72,8 @@ def parse():
                     help="a general matrix: the same graph with seeded signed weights, column l1 norm 0.85")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="skip the autotuned solve (library tuner, run before its own timing)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -334,6 +336,39 @@ def warm_bench(ctx, dev, epochs=40):
     }
 
 
+def tuned_bench(ctx, cpt, rit, bt, ht, ft, args, nnz):
+    """The same solve with the options the library's tuner picks for this
+    problem (partition type and size, alpha, local sweeps, refresh point);
+    the tuning runs before, outside the timing."""
+    import torch
+    from paper_1202_6168_amd import ditr
+
+    t0 = time.perf_counter()
+    o, info = ditr.tune(ctx, cpt, rit, bt, ht, ft, rel_tol=args.tol, effort=1)
+    tune_s = time.perf_counter() - t0
+    g = ditr.Graph(ctx, cpt, rit, opts=ditr.opts_default(part_type=o.part_type, part_nodes=o.part_nodes))
+    for _ in range(args.warmup):
+        ditr.solve(ctx, g, bt, ht, ft, rel_tol=args.tol, opts=o, allow=(ditr.OK,))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = [ditr.solve(ctx, g, bt, ht, ft, rel_tol=args.tol, opts=o, allow=(ditr.OK,)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    g.close()
+    edges = sum(s.edges for s in st)
+    return {
+        "ms_per_step": 1e3 * wall / args.steps,
+        "edges_per_s": edges / wall,
+        "levels_per_step": sum(s.sweeps for s in st) / args.steps,
+        "normalized_iterations": edges / args.steps / nnz,
+        "final_resid_rel": st[-1].resid_l1 / st[-1].b_l1,
+        "options": {"alpha": o.alpha, "part_type": o.part_type, "part_nodes": o.part_nodes,
+                    "sweeps_per_level": o.sweeps_per_claim, "refresh_at": o.refresh_at},
+        "tuner_seconds": tune_s,
+        "tuner_candidates": info.candidates,
+    }
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -461,6 +496,8 @@ def main():
     }
     if resident and args.mode in (0, 3) and not args.weighted:
         out["trace"] = trace_summary(ctx, g, bt, ht, ft, args.tol, opts, K, dev)
+    if not args.no_tuned and not args.large and args.mode == 0 and not args.weighted and not args.priority:
+        out["tuned"] = tuned_bench(ctx, cpt, rit, bt, ht, ft, args, ri.size)
     if not args.no_batched:
         out["batched"] = batched_bench(ctx, g, spec.n, dev)
     g.close()
