@@ -242,6 +242,120 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp(int64_t n, int64_t K, const 
   }
 }
 
+// (value, position) with the smaller position first among equal values
+struct McMin {
+  long long v;
+  int32_t p;
+};
+__device__ __forceinline__ McMin mc_min(McMin a, McMin b) { return (b.v < a.v || (b.v == a.v && b.p < a.p)) ? b : a; }
+
+// The same programme with the previous window staged in LDS (values, cost
+// prefix, suffix-minimum positions: 20 bytes per position), for windows of at
+// most `wmax` positions. The suffix minimum runs in place: each thread a chunk
+// from its right end, then across the chunks with wave shuffles and one LDS
+// round for the sixteen waves; the binary searches read the staged prefix.
+__global__ void __launch_bounds__(kMcBlock) k_mc_dp_lds(int64_t n, int64_t K, const long long* __restrict__ C,
+                                                      const unsigned long long* __restrict__ cross,
+                                                      const long long* __restrict__ lo,
+                                                      const long long* __restrict__ hi,
+                                                      const long long* __restrict__ off, long long cmax,
+                                                      long long smax, int wmax, long long* Va, long long* Vb,
+                                                      int32_t* back, int64_t* out64, int32_t* out32, int* err) {
+  extern __shared__ __align__(16) unsigned char mc_smem[];
+  long long* sV = reinterpret_cast<long long*>(mc_smem);
+  long long* sC = sV + wmax;
+  int32_t* sP = reinterpret_cast<int32_t*>(sC + wmax);
+  __shared__ long long w_v[kMcBlock / 64];
+  __shared__ int32_t w_p[kMcBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  long long* Vp = Va;
+  long long* Vc = Vb;
+  if (tid == 0) Vp[0] = 0;  // window 0 is {0}
+  __syncthreads();
+  for (int64_t k = 1; k <= K; ++k) {
+    const long long plo = lo[k - 1], phi = hi[k - 1];
+    const int pm = (int)(phi - plo + 1);
+    for (int i = tid; i < pm; i += kMcBlock) {
+      sV[i] = Vp[i];
+      sC[i] = C[plo + i];
+    }
+    __syncthreads();
+    // suffix minimum within each thread's chunk, in place
+    const int ch = (pm + kMcBlock - 1) / kMcBlock;
+    const int c0 = tid * ch, c1 = c0 + ch < pm ? c0 + ch : pm;
+    McMin run{kMcInf, -1};
+    for (int i = c1 - 1; i >= c0; --i) {
+      run = mc_min(run, McMin{sV[i], (int32_t)(plo + i)});
+      sV[i] = run.v;
+      sP[i] = run.p;
+    }
+    // minimum over the chunks to the right: inclusive suffix scan in the wave,
+    // shifted by one lane, then the waves to the right
+    McMin inc = run;
+    for (int d = 1; d < 64; d <<= 1) {
+      McMin o;
+      o.v = __shfl_down(inc.v, d, 64);
+      o.p = __shfl_down(inc.p, d, 64);
+      if (lane + d < 64) inc = mc_min(inc, o);
+    }
+    McMin excl;
+    excl.v = __shfl_down(inc.v, 1, 64);
+    excl.p = __shfl_down(inc.p, 1, 64);
+    if (lane == 63) excl = McMin{kMcInf, -1};
+    if (lane == 0) {
+      w_v[wave] = inc.v;
+      w_p[wave] = inc.p;
+    }
+    __syncthreads();
+    for (int w = wave + 1; w < kMcBlock / 64; ++w) excl = mc_min(excl, McMin{w_v[w], w_p[w]});
+    for (int i = c0; i < c1; ++i) {
+      const McMin m = mc_min(McMin{sV[i], sP[i]}, excl);
+      sV[i] = m.v;
+      sP[i] = m.p;
+    }
+    __syncthreads();
+    // the current window
+    const long long clo = lo[k], cm = hi[k] - clo + 1;
+    for (long long j = tid; j < cm; j += kMcBlock) {
+      const long long b = clo + j;
+      int a = (int)((b - smax > plo ? b - smax : plo) - plo), z = pm;
+      const long long need = C[b] - cmax;  // first q with C(q) >= C(b) - cmax
+      while (a < z) {
+        const int mid = (a + z) >> 1;
+        if (sC[mid] < need) a = mid + 1; else z = mid;
+      }
+      long long v = kMcInf;
+      int32_t q = -1;
+      if (a < pm) {
+        v = sV[a];
+        q = sP[a];
+      }
+      Vc[j] = v >= kMcInf ? kMcInf : v + (k < K ? (long long)cross[b] : 0);
+      back[off[k] + j] = v >= kMcInf ? -1 : q;
+    }
+    __syncthreads();
+    long long* t = Vp;
+    Vp = Vc;
+    Vc = t;
+  }
+  if (tid == 0) {
+    long long b = n;
+    if (out64) out64[K] = n;
+    if (out32) out32[K] = (int32_t)n;
+    for (int64_t k = K; k >= 1; --k) {
+      const int32_t q = back[off[k] + (b - lo[k])];
+      if (q < 0) {
+        *err = 1;
+        return;
+      }
+      b = q;
+      if (out64) out64[k - 1] = b;
+      if (out32) out32[k - 1] = (int32_t)b;
+    }
+    if (b != 0) *err = 1;
+  }
+}
+
 struct McSizes {
   size_t scan_n = 0, scan_k = 0, scan_x = 0;
 };
@@ -319,8 +433,19 @@ int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* 
       hipStreamSynchronize(st) != hipSuccess)
     return done(set_error(DITR_EHIP, "cut-minimizing partition setup failed"));
   const long long cmax = (long long)hl[0] + (long long)hl[0] / 10, smax = (long long)hl[1] + (long long)hl[1] / 10;
-  k_mc_dp<<<1, kMcBlock, 0, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, Va, Vb, smv, smi, back, out64, out32,
-                                  err);
+  // the previous window in LDS when it fits (20 bytes per position), else in
+  // global memory
+  const size_t lds = 20 * win;
+  bool in_lds = lds <= 150 * 1024 &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mc_dp_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
+  if (!in_lds) (void)hipGetLastError();
+  if (in_lds)
+    k_mc_dp_lds<<<1, kMcBlock, lds, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, (int)win, Va, Vb, back, out64,
+                                          out32, err);
+  else
+    k_mc_dp<<<1, kMcBlock, 0, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, Va, Vb, smv, smi, back, out64, out32,
+                                    err);
   int herr = 0;
   if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
