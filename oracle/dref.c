@@ -377,6 +377,12 @@ int dref_partition_pmass(int64_t n, int64_t nnz, const int32_t* col_ptr, const i
  *   - boundary k moves within [t_k - w_k, t_k + w_k], w_k = min(ceil(N/K)/2,
  *     half of each neighbouring target gap less one), so the windows are
  *     disjoint and the CB targets stay feasible;
+ *   - no boundary falls inside a short tight cycle when a plan exists
+ *     without that: a directed cycle of two or three distinct nodes whose
+ *     out-degrees multiply to at most 2 (it hands back at least 0.85^len / 2
+ *     of its fluid per round, so split across two sets its fluid would cross
+ *     back and forth one level per hop), spanning fewer than 2 ceil(N/K) ids;
+ *     a boundary b lies inside the cycle when min < b <= max of its ids;
  *   - the plan minimizes the sum of cross(b_k) over the inner boundaries;
  *     among plans of equal sum, b_{K-1} is the smallest possible, then
  *     b_{K-2}, and so on (a dynamic programme over the windows whose
@@ -430,6 +436,37 @@ int dref_partition_mincut(int64_t n, int64_t nnz, const int32_t* col_ptr, const 
       cross[z + 1] -= u;
     }
   for (int64_t b = 1; b <= n; ++b) cross[b] += cross[b - 1];
+  /* positions inside a short tight cycle: a directed cycle of two or three
+     distinct nodes whose out-degrees multiply to at most 2, so that it hands
+     back at least 0.85^len / 2 of its fluid per round */
+  int64_t* tight = (int64_t*)calloc((size_t)n + 2, sizeof(int64_t));
+  if (!tight) {
+    free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+    return DREF_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t oi = col_ptr[i + 1] - col_ptr[i];
+    if (oi < 1 || oi > 2) continue;
+    for (int64_t e1 = col_ptr[i]; e1 < col_ptr[i + 1]; ++e1) {
+      const int64_t j = row_idx[e1], oj = col_ptr[j + 1] - col_ptr[j];
+      if (j <= i || oi * oj > 2) continue;
+      for (int64_t e2 = col_ptr[j]; e2 < col_ptr[j + 1]; ++e2) {
+        const int64_t k = row_idx[e2];
+        if (k == i) { /* i -> j -> i */
+          if (j - i < span) tight[i + 1] += 1, tight[j + 1] -= 1;
+          continue;
+        }
+        const int64_t ok = col_ptr[k + 1] - col_ptr[k];
+        if (k <= i || k == j || oi * oj * ok > 2) continue;
+        for (int64_t e3 = col_ptr[k]; e3 < col_ptr[k + 1]; ++e3)
+          if (row_idx[e3] == i) { /* i -> j -> k -> i */
+            const int64_t z = j > k ? j : k;
+            if (z - i < span) tight[i + 1] += 1, tight[z + 1] -= 1;
+          }
+      }
+    }
+  }
+  for (int64_t b = 1; b <= n; ++b) tight[b] += tight[b - 1];
   /* windows */
   const int64_t W = mean / 2;
   for (int64_t k = 1; k < K; ++k) {
@@ -447,28 +484,34 @@ int dref_partition_mincut(int64_t n, int64_t nnz, const int32_t* col_ptr, const 
   int64_t* V = (int64_t*)malloc(sizeof(int64_t) * (size_t)off[K + 1]);
   int64_t* P = (int64_t*)malloc(sizeof(int64_t) * (size_t)off[K + 1]);
   if (!V || !P) {
-    free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+    free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off), free(tight);
     return DREF_ENOMEM;
   }
   const int64_t INF = INT64_MAX / 4;
-  V[0] = 0;
-  P[0] = -1;
-  /* V[k][b]: least sum of cross over boundaries 1..k with b_k = b */
-  for (int64_t k = 1; k <= K; ++k) {
-    for (int64_t b = lo[k]; b <= hi[k]; ++b) {
-      int64_t best = INF, arg = -1;
-      for (int64_t q = lo[k - 1]; q <= hi[k - 1]; ++q) {
-        const int64_t v = V[off[k - 1] + q - lo[k - 1]];
-        if (v >= INF || b - q > smax || C[b] - C[q] > cmax) continue;
-        if (v < best) best = v, arg = q;   /* strict: the smallest q among equals */
+  /* V[k][b]: least sum of cross over boundaries 1..k with b_k = b; the first
+     pass admits no boundary inside a tight cycle, the second (only when the
+     first finds no plan) admits every position */
+  for (int pass = 0; pass < 2; ++pass) {
+    V[0] = 0;
+    P[0] = -1;
+    for (int64_t k = 1; k <= K; ++k) {
+      for (int64_t b = lo[k]; b <= hi[k]; ++b) {
+        int64_t best = INF, arg = -1;
+        for (int64_t q = lo[k - 1]; q <= hi[k - 1]; ++q) {
+          const int64_t v = V[off[k - 1] + q - lo[k - 1]];
+          if (v >= INF || b - q > smax || C[b] - C[q] > cmax) continue;
+          if (v < best) best = v, arg = q; /* strict: the smallest q among equals */
+        }
+        if (pass == 0 && k < K && tight[b] > 0) best = INF;
+        V[off[k] + b - lo[k]] = best >= INF ? INF : best + (k < K ? cross[b] : 0);
+        P[off[k] + b - lo[k]] = arg;
       }
-      V[off[k] + b - lo[k]] = best >= INF ? INF : best + (k < K ? cross[b] : 0);
-      P[off[k] + b - lo[k]] = arg;
     }
+    if (V[off[K]] < INF) break;
   }
   /* back from b_K = n (the CB targets are feasible, so V[K][n] is finite) */
   ptr[K] = n;
   for (int64_t k = K; k >= 1; --k) ptr[k - 1] = P[off[k] + ptr[k] - lo[k]];
-  free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off);
+  free(V), free(P), free(C), free(indeg), free(cross), free(t), free(lo), free(hi), free(off), free(tight);
   return ptr[0] == 0 ? DREF_OK : DREF_EINVAL;
 }

@@ -56,7 +56,25 @@ def reference_parts(cp, ri, K):
     for k in range(1, K):
         w = max(0, min(W, (t[k] - t[k - 1] - 1) // 2, (t[k + 1] - t[k] - 1) // 2))
         wins.append(range(t[k] - w, t[k] + w + 1))
-    return dict(C=C, t=t, cmax=cmax, smax=smax, cross=cross, wins=wins)
+    # positions inside a short tight cycle: every directed cycle of 2 or 3
+    # distinct nodes, found from the adjacency sets, whose out-degrees multiply
+    # to at most 2
+    succ = [set(int(x) for x in ri[cp[i]:cp[i + 1]]) for i in range(n)]
+    forbidden = set()
+    for i in range(n):
+        for j in succ[i]:
+            if j == i:
+                continue
+            cyc = []
+            if i in succ[j]:
+                cyc.append((i, j))
+            for k in succ[j]:
+                if k not in (i, j) and i in succ[k]:
+                    cyc.append((i, j, k))
+            for c in cyc:
+                if np.prod([outd[x] for x in c]) <= 2 and max(c) - min(c) < span:
+                    forbidden.update(range(min(c) + 1, max(c) + 1))
+    return dict(C=C, t=t, cmax=cmax, smax=smax, cross=cross, wins=wins, forbidden=forbidden)
 
 
 def feasible(ptr, ref):
@@ -66,17 +84,22 @@ def feasible(ptr, ref):
 
 
 def brute_plan(cp, ri, K):
+    """The optimum over every feasible plan; plans with no boundary inside a
+    tight cycle first, all plans only when there is none such."""
     n = cp.size - 1
     ref = reference_parts(cp, ri, K)
-    best = None
+    best = [None, None]
     for inner in itertools.product(*ref["wins"]):
         ptr = [0, *inner, n]
         if not feasible(ptr, ref):
             continue
         key = (sum(ref["cross"][b] for b in inner), tuple(reversed(inner)))
-        if best is None or key < best[0]:
-            best = (key, ptr)
-    return best[1], best[0][0], ref
+        clean = not any(b in ref["forbidden"] for b in inner)
+        for slot in ((0, 1) if clean else (1,)):
+            if best[slot] is None or key < best[slot][0]:
+                best[slot] = (key, ptr)
+    b = best[0] if best[0] is not None else best[1]
+    return b[1], b[0][0], ref
 
 
 def local_graph(n, rng, reach=4, p_out=0.5, dangling_frac=0.1):
@@ -184,6 +207,51 @@ def cycle_blocks(sizes):
             edges.append((a + i, a + (i + 2) % s))
         a += s
     return csc_from_edges(a, edges), np.cumsum([0] + list(sizes))
+
+
+def planted_cycle(seed):
+    """A sparse local graph with a 2-cycle (odd seeds) or a 3-cycle (even
+    seeds) of out-degree-1 nodes planted around the first CB target."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(24, 40))
+    K = int(rng.integers(2, 4))
+    cp, ri = local_graph(n, rng, reach=3, p_out=0.15, dangling_frac=0.05)
+    edges = [(s_, int(t)) for s_ in range(n) for t in ri[cp[s_]:cp[s_ + 1]]]
+    m = n // K
+    cyc = [m - 1, m + 1] if seed % 2 else [m - 2, m, m + 1]
+    edges = [(s_, t) for (s_, t) in edges if s_ not in cyc]
+    edges += list(zip(cyc, cyc[1:] + cyc[:1]))
+    return csc_from_edges(n, edges), K
+
+
+@pytest.mark.parametrize("seed", [23, 76, 103, 184])
+def test_mincut_keeps_tight_cycles_whole(seed):
+    # on these graphs the least crossing mass alone would split the cycle
+    (cp, ri), K = planted_cycle(seed)
+    n = cp.size - 1
+    ref = reference_parts(cp, ri, K)
+    got = oracle.partition_mincut(cp, ri, K).tolist()
+    assert got == brute_plan(cp, ri, K)[0]
+    assert ref["forbidden"] and not any(b in ref["forbidden"] for b in got[1:-1])
+    plain = min(([0, *inner, n] for inner in itertools.product(*ref["wins"])
+                 if feasible([0, *inner, n], ref)),
+                key=lambda p: (sum(ref["cross"][b] for b in p[1:-1]), tuple(reversed(p[1:-1]))))
+    assert plain != got and any(b in ref["forbidden"] for b in plain[1:-1])
+
+
+@pytest.mark.parametrize("degrees,tight", [((1, 1), True), ((1, 2), True), ((2, 2), False),
+                                           ((1, 1, 1), True), ((1, 1, 2), True), ((1, 2, 2), False)])
+def test_tight_cycle_definition(degrees, tight):
+    # a cycle over ids 10, 13 (, 16) of a 30-node graph; extra out-links of a
+    # cycle node go to a far dangling node, so only the cycle's own degrees count
+    ids = [10, 13, 16][:len(degrees)]
+    edges = list(zip(ids, ids[1:] + ids[:1]))
+    for x, dg in zip(ids, degrees):
+        edges += [(x, 29)] * (dg - 1)
+    cp, ri = csc_from_edges(30, edges)
+    ref = reference_parts(cp, ri, 2)
+    assert (ref["forbidden"] == set(range(11, ids[-1] + 1))) == tight
+    assert (not ref["forbidden"]) == (not tight)
 
 
 def test_mincut_cuts_nothing_between_disjoint_blocks():

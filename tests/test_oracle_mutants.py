@@ -64,6 +64,11 @@ MUTANTS = {
     "mincut_window_one_wider": ("lo[k] = t[k] - w;\n    hi[k] = t[k] + w;", "lo[k] = t[k] - w - 1;\n    hi[k] = t[k] + w + 1;"),
     "mincut_crossing_off_by_one": ("cross[a + 1] += u; /* the link", "cross[a] += u; /* the link"),
     "mincut_crossing_end_kept": ("      cross[z + 1] -= u;\n", "      cross[z] -= u;\n"),
+    "mincut_tight_cycles_ignored": ("if (pass == 0 && k < K && tight[b] > 0) best = INF;",
+                                    "if (pass == 0 && k < K && tight[b] < 0) best = INF;"),
+    "mincut_three_cycles_ignored": ("if (k <= i || k == j || oi * oj * ok > 2) continue;", "if (1) continue;"),
+    "mincut_tight_span_from_min": ("if (j - i < span) tight[i + 1] += 1, tight[j + 1] -= 1;",
+                                   "if (j - i < span) tight[i] += 1, tight[j + 1] -= 1;"),
 }
 
 
@@ -218,6 +223,15 @@ def general_pin_suite(lib):
             got = None
         if got != tm.brute_plan(xcp, xri, K)[0]:
             fails.append("mincut_mixed")
+            break
+    for seed in (23, 76, 103, 184):
+        (pcp, pri), K = tm.planted_cycle(seed)
+        try:
+            got = oracle.partition_mincut(pcp, pri, K, lib=lib).tolist()
+        except ValueError:
+            got = None
+        if got != tm.brute_plan(pcp, pri, K)[0]:
+            fails.append("mincut_tight")
             break
     ecp, eri = csc_from_edges(40, [])
     try:
