@@ -251,6 +251,9 @@ int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, i
  *     floor(0.85 / #out_i * 2^32); cross(b) sums those with min < b <= max;
  *   - boundary k lies in [t_k - w_k, t_k + w_k], w_k = min(ceil(n/K)/2,
  *     (t_k - t_{k-1} - 1)/2, (t_{k+1} - t_k - 1)/2), at least 0;
+ *   - when a plan exists that way, no boundary b has min < b <= max for a
+ *     tight cycle: a directed 2- or 3-cycle of distinct nodes whose
+ *     out-degrees multiply to at most 2, spanning fewer than 2 ceil(n/K) ids;
  *   - the plan minimizes sum_k cross(b_k); among equal sums b_{K-1} is the
  *     smallest possible, then b_{K-2}, and so on.
  * Takes device temporaries of about 32 bytes per node; EINVAL if no plan is

@@ -18,12 +18,19 @@
 //   * boundary k lies in [t_k - w_k, t_k + w_k], w_k = min(ceil(N/K) / 2, half
 //     of each neighbouring target gap less one): the windows are disjoint and
 //     the targets themselves are a feasible plan;
+//   * no boundary lies inside a short tight cycle (a directed cycle of two or
+//     three distinct nodes whose out-degrees multiply to at most 2, spanning
+//     fewer than 2 ceil(N/K) ids; b is inside when min < b <= max) when a
+//     plan exists without that: split across two sets, such a cycle hands its
+//     fluid back one level per hop;
 //   * the plan minimizes the sum of cross(b_k); among equal sums the last
 //     boundary is the smallest possible, then the one before, and so on.
 //
 // Device plan: the costs and their scan, the targets by binary search, the
 // crossing mass as a difference array (two atomics per short link, one per
-// column for the end at the column's own id) and its scan, then a dynamic
+// column for the end at the column's own id) and its scan, the tight cycles
+// counted over each position the same way (each found from its smallest
+// node, whose out-degree is 1 or 2), then a dynamic
 // programme in one workgroup, one window per step: a suffix minimum (value,
 // position) of the previous window, and each position of the current window
 // takes the best predecessor its balance limits admit (a binary search on
@@ -141,6 +148,43 @@ __global__ void k_mc_cross(int64_t n, long long span, const int32_t* __restrict_
   }
 }
 
+// tight cycles: +1 at min + 1, -1 at max + 1 for each one found from its
+// smallest node i (every path of CSC entries i -> j -> i or i -> j -> k -> i)
+__global__ void k_mc_tight(int64_t n, long long span, const int32_t* __restrict__ col_ptr,
+                           const int32_t* __restrict__ row_idx, int* tdiff) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int oi = col_ptr[i + 1] - col_ptr[i];
+    if (oi < 1 || oi > 2) continue;
+    for (int32_t e1 = col_ptr[i]; e1 < col_ptr[i + 1]; ++e1) {
+      const int64_t j = row_idx[e1];
+      const int oj = col_ptr[j + 1] - col_ptr[j];
+      if (j <= i || oi * oj > 2) continue;
+      for (int32_t e2 = col_ptr[j]; e2 < col_ptr[j + 1]; ++e2) {
+        const int64_t k = row_idx[e2];
+        if (k == i) {  // i -> j -> i
+          if (j - i < span) {
+            atomicAdd(&tdiff[i + 1], 1);
+            atomicAdd(&tdiff[j + 1], -1);
+          }
+          continue;
+        }
+        if (k <= i || k == j) continue;
+        const int ok = col_ptr[k + 1] - col_ptr[k];
+        if (oi * oj * ok > 2) continue;
+        for (int32_t e3 = col_ptr[k]; e3 < col_ptr[k + 1]; ++e3)
+          if (row_idx[e3] == i) {  // i -> j -> k -> i
+            const int64_t z = j > k ? j : k;
+            if (z - i < span) {
+              atomicAdd(&tdiff[i + 1], 1);
+              atomicAdd(&tdiff[z + 1], -1);
+            }
+          }
+      }
+    }
+  }
+}
+
 // The dynamic programme (one workgroup). Va/Vb: values of the previous and
 // the current window; smv/smi: suffix minimum of the previous window (value,
 // position); back: the chosen predecessor of every window position, at
@@ -149,8 +193,9 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp(int64_t n, int64_t K, const 
                                                   const unsigned long long* __restrict__ cross,
                                                   const long long* __restrict__ lo, const long long* __restrict__ hi,
                                                   const long long* __restrict__ off, long long cmax, long long smax,
-                                                  long long* Va, long long* Vb, long long* smv, int32_t* smi,
-                                                  int32_t* back, int64_t* out64, int32_t* out32, int* err) {
+                                                  const int* __restrict__ tight, int keep_tight, long long* Va,
+                                                  long long* Vb, long long* smv, int32_t* smi, int32_t* back,
+                                                  int64_t* out64, int32_t* out32, int* err) {
   __shared__ long long s_val[kMcBlock];
   __shared__ int32_t s_pos[kMcBlock];
   const int tid = threadIdx.x;
@@ -212,7 +257,7 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp(int64_t n, int64_t K, const 
       }
       long long v = kMcInf;
       int32_t p = -1;
-      if (a <= phi) {
+      if (a <= phi && !(keep_tight && k < K && tight[b] > 0)) {
         v = smv[a - plo];
         p = smi[a - plo];
       }
@@ -259,8 +304,9 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp_lds(int64_t n, int64_t K, co
                                                       const long long* __restrict__ lo,
                                                       const long long* __restrict__ hi,
                                                       const long long* __restrict__ off, long long cmax,
-                                                      long long smax, int wmax, long long* Va, long long* Vb,
-                                                      int32_t* back, int64_t* out64, int32_t* out32, int* err) {
+                                                      long long smax, const int* __restrict__ tight, int keep_tight,
+                                                      int wmax, long long* Va, long long* Vb, int32_t* back,
+                                                      int64_t* out64, int32_t* out32, int* err) {
   extern __shared__ __align__(16) unsigned char mc_smem[];
   long long* sV = reinterpret_cast<long long*>(mc_smem);
   long long* sC = sV + wmax;
@@ -326,7 +372,7 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp_lds(int64_t n, int64_t K, co
       }
       long long v = kMcInf;
       int32_t q = -1;
-      if (a < pm) {
+      if (a < pm && !(keep_tight && k < K && tight[b] > 0)) {
         v = sV[a];
         q = sP[a];
       }
@@ -357,7 +403,7 @@ __global__ void __launch_bounds__(kMcBlock) k_mc_dp_lds(int64_t n, int64_t K, co
 }
 
 struct McSizes {
-  size_t scan_n = 0, scan_k = 0, scan_x = 0;
+  size_t scan_n = 0, scan_k = 0, scan_x = 0, scan_t = 0;
 };
 
 McSizes mc_scan_sizes(int64_t n, int64_t K) {
@@ -366,6 +412,7 @@ McSizes mc_scan_sizes(int64_t n, int64_t K) {
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, s.scan_x, (unsigned long long*)nullptr,
                                          (unsigned long long*)nullptr, (int)(n + 1));
   (void)hipcub::DeviceScan::ExclusiveSum(nullptr, s.scan_k, (long long*)nullptr, (long long*)nullptr, (int)(K + 2));
+  (void)hipcub::DeviceScan::InclusiveSum(nullptr, s.scan_t, (int*)nullptr, (int*)nullptr, (int)(n + 1));
   return s;
 }
 
@@ -400,16 +447,17 @@ int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* 
   long long *cst, *C, *t, *lo, *hi, *size, *off, *Va, *Vb, *smv;
   unsigned long long *cross, *lim;
   int32_t *smi, *back;
-  int* err;
-  void *tn, *tk, *tx;
+  int *err, *tdiff, *tight;
+  void *tn, *tk, *tx, *tt;
   if (!alloc((void**)&cst, 8 * (n + 1)) || !alloc((void**)&C, 8 * (n + 1)) || !alloc((void**)&cross, 8 * (n + 1)) ||
       !alloc((void**)&t, 8 * (K + 1)) || !alloc((void**)&lo, 8 * (K + 1)) || !alloc((void**)&hi, 8 * (K + 1)) ||
       !alloc((void**)&size, 8 * (K + 2)) || !alloc((void**)&off, 8 * (K + 2)) || !alloc((void**)&lim, 16) ||
       !alloc((void**)&Va, 8 * win) || !alloc((void**)&Vb, 8 * win) || !alloc((void**)&smv, 8 * win) ||
       !alloc((void**)&smi, 4 * win) || !alloc((void**)&back, 4 * nback) || !alloc((void**)&err, 4) ||
-      !alloc(&tn, ss.scan_n) || !alloc(&tk, ss.scan_k) || !alloc(&tx, ss.scan_x))
+      !alloc((void**)&tdiff, 4 * (n + 1)) || !alloc((void**)&tight, 4 * (n + 1)) || !alloc(&tn, ss.scan_n) ||
+      !alloc(&tk, ss.scan_k) || !alloc(&tx, ss.scan_x) || !alloc(&tt, ss.scan_t))
     return done(set_error(DITR_ENOMEM, "device allocation failed (cut-minimizing partition)"));
-  size_t bn = ss.scan_n, bk = ss.scan_k, bx = ss.scan_x;
+  size_t bn = ss.scan_n, bk = ss.scan_k, bx = ss.scan_x, bt = ss.scan_t;
   // costs, their prefix, the targets, the balance limits and the windows
   k_mc_cost<<<mc_grid(n + 1, 256, 16384), 256, 0, st>>>(n, col_ptr, in_ptr, h, cst);
   if (hipcub::DeviceScan::ExclusiveSum(tn, bn, cst, C, (int)(n + 1), st) != hipSuccess)
@@ -428,6 +476,12 @@ int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* 
   if (nnz > 0) k_mc_cross<<<mc_grid(n, 256, 16384), 256, 0, st>>>(n, span, col_ptr, row_idx, diff);
   if (hipcub::DeviceScan::InclusiveSum(tx, bx, diff, cross, (int)(n + 1), st) != hipSuccess)
     return done(set_error(DITR_EHIP, "crossing scan failed"));
+  // tight cycles over every position
+  if (hipMemsetAsync(tdiff, 0, 4 * (n + 1), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "hipMemsetAsync failed"));
+  if (nnz > 0) k_mc_tight<<<mc_grid(n, 256, 16384), 256, 0, st>>>(n, span, col_ptr, row_idx, tdiff);
+  if (hipcub::DeviceScan::InclusiveSum(tt, bt, tdiff, tight, (int)(n + 1), st) != hipSuccess)
+    return done(set_error(DITR_EHIP, "tight-cycle scan failed"));
   unsigned long long hl[2] = {0, 0};
   if (hipGetLastError() != hipSuccess || hipMemcpyAsync(hl, lim, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -440,16 +494,22 @@ int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* 
                 hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mc_dp_lds),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) == hipSuccess;
   if (!in_lds) (void)hipGetLastError();
-  if (in_lds)
-    k_mc_dp_lds<<<1, kMcBlock, lds, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, (int)win, Va, Vb, back, out64,
-                                          out32, err);
-  else
-    k_mc_dp<<<1, kMcBlock, 0, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, Va, Vb, smv, smi, back, out64, out32,
-                                    err);
+  // first with no boundary inside a tight cycle; when that leaves no plan,
+  // again with every position admitted
   int herr = 0;
-  if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return done(set_error(DITR_EHIP, "cut-minimizing partition failed"));
+  for (int keep = 1; keep >= 0; --keep) {
+    if (hipMemsetAsync(err, 0, 4, st) != hipSuccess) return done(set_error(DITR_EHIP, "hipMemsetAsync failed"));
+    if (in_lds)
+      k_mc_dp_lds<<<1, kMcBlock, lds, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, tight, keep, (int)win, Va, Vb,
+                                            back, out64, out32, err);
+    else
+      k_mc_dp<<<1, kMcBlock, 0, st>>>(n, K, C, cross, lo, hi, off, cmax, smax, tight, keep, Va, Vb, smv, smi, back,
+                                      out64, out32, err);
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return done(set_error(DITR_EHIP, "cut-minimizing partition failed"));
+    if (!herr) break;
+  }
   if (herr) return done(set_error(DITR_EINVAL, "cut-minimizing partition found no plan"));
   return done(DITR_OK);
 }
@@ -461,7 +521,7 @@ size_t mincut_temp_bytes(int64_t n, int64_t K) {
   const McSizes ss = mc_scan_sizes(n, K);
   const size_t N = (size_t)n, KK = (size_t)std::max<int64_t>(K, 1);
   const size_t W = ((N + KK - 1) / KK) / 2;
-  return 3 * al(8 * (N + 1)) + 3 * al(8 * (KK + 1)) + 2 * al(8 * (KK + 2)) + al(16) + 3 * al(8 * (2 * W + 2)) +
-         al(4 * (2 * W + 2)) + al(4 * (KK + 1) * (2 * W + 1)) + al(4) + al(ss.scan_n) + al(ss.scan_k) +
-         al(ss.scan_x) + 4096;
+  return 3 * al(8 * (N + 1)) + 2 * al(4 * (N + 1)) + 3 * al(8 * (KK + 1)) + 2 * al(8 * (KK + 2)) + al(16) +
+         3 * al(8 * (2 * W + 2)) + al(4 * (2 * W + 2)) + al(4 * (KK + 1) * (2 * W + 1)) + al(4) + al(ss.scan_n) +
+         al(ss.scan_k) + al(ss.scan_x) + al(ss.scan_t) + 4096;
 }

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1202_6168_amd import ditr  # noqa: E402
 from test_gpu_solve import ADV, check_parity, gpu_solve, upload  # noqa: E402
-from test_oracle_mincut import hub_graph, local_graph, mixed_case  # noqa: E402
+from test_oracle_mincut import hub_graph, local_graph, mixed_case, planted_cycle  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -37,6 +37,9 @@ def _graphs():
     out.append(("hubs_38", *hub_graph(38, np.random.default_rng(51))))
     cp, ri, _ = mixed_case(17)
     out.append(("mixed_17", cp, ri))
+    for seed in (23, 76):
+        (pcp, pri), _ = planted_cycle(seed)
+        out.append(("tight_%d" % seed, pcp, pri))
     out.append(("web_1e4", *ditgen.generate(ditgen.GraphSpec(n=10_000, block=100, seed=1))))
     out.append(("web_5e4", *ditgen.generate(ditgen.GraphSpec(n=50_000, block=1000, seed=2))))
     out.append(("web_2e5_ragged", *ditgen.generate(ditgen.GraphSpec(n=200_003, block=700, seed=6))))
@@ -49,7 +52,7 @@ GRAPHS = _graphs()
 
 
 @pytest.mark.parametrize("case", GRAPHS, ids=[g[0] for g in GRAPHS])
-@pytest.mark.parametrize("K", [1, 2, 5, 64, 256])
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 64, 256])
 def test_mincut_partition_bit_exact(ctx, case, K):
     name, cp, ri = case
     n = cp.size - 1
