@@ -33,8 +33,8 @@ PROFILE = os.path.join(ROOT, "profiles", "k_part_resident_headline_n1e6.json")
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary
-    covers another kernel or the kernel source changed since those counters
-    were taken."""
+    covers another kernel or the kernel or plan source changed since those
+    counters were taken."""
     import hashlib
 
     try:
@@ -44,6 +44,13 @@ def profiled_traffic(kernel):
         return None
     if hashlib.sha256(src).hexdigest() != prof.get("source_sha256"):
         return None
+    if "plan_source" in prof:  # the counters also depend on the partition plan
+        try:
+            plan = open(os.path.join(ROOT, prof["plan_source"]), "rb").read()
+        except OSError:
+            return None
+        if hashlib.sha256(plan).hexdigest() != prof.get("plan_source_sha256"):
+            return None
     if prof.get("kernel", "").split("<")[0] != kernel:
         return None
     return prof["traffic_bytes_per_launch"]
