@@ -30,11 +30,13 @@
 // crossing mass as a difference array (two atomics per short link, one per
 // column for the end at the column's own id) and its scan, the tight cycles
 // counted over each position the same way (each found from its smallest
-// node, whose out-degree is 1 or 2), then a dynamic
-// programme in one workgroup, one window per step: a suffix minimum (value,
-// position) of the previous window, and each position of the current window
-// takes the best predecessor its balance limits admit (a binary search on
-// C). Back-pointers hold the smallest predecessor among equals.
+// node, whose out-degree is 1 or 2), then a dynamic programme in one
+// workgroup, one window per step: a suffix minimum (value, position) of the
+// previous window, and each position of the current window takes the best
+// predecessor its balance limits admit (a binary search on C). The previous
+// window sits in LDS when it fits. Back-pointers hold the smallest
+// predecessor among equals. The programme runs a second time, admitting
+// every position, only when the first finds no plan.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
