@@ -49,6 +49,15 @@ int set_error(int code, const char* fmt, ...) {
   return code;
 }
 
+// the partition count a plan starts from (the plan loop only raises it):
+// part_nodes per partition, or about 4096 nodes per partition and at least one
+// partition per CU when n allows
+int64_t initial_parts(const ditr_ctx* c, int64_t n, int32_t part_nodes) {
+  int64_t K = part_nodes > 0 ? (n + part_nodes - 1) / part_nodes
+                             : std::max<int64_t>((n + 4095) / 4096, std::min<int64_t>(c->num_cus, n / 256));
+  return std::max<int64_t>(1, std::min<int64_t>(K, n));
+}
+
 extern "C" {
 
 int ditr_version(void) { return DITR_ABI_VERSION; }
@@ -390,14 +399,7 @@ static int graph_create_impl(ditr_ctx* c, ditr_graph** out, int64_t n, int64_t n
   const int64_t cap_nodes = std::min<int64_t>(
       65536, std::min<int64_t>((int64_t)((lds_max - 16) / 12), (int64_t)((c->part_lds_dyn - 64) / 20)));
   g->cap_nodes = cap_nodes;
-  int64_t K;
-  if (o.part_nodes > 0) {
-    K = (n + o.part_nodes - 1) / o.part_nodes;
-  } else {
-    // about 4096 nodes per partition, and at least one partition per CU when n allows
-    K = std::max<int64_t>((n + 4095) / 4096, std::min<int64_t>(c->num_cus, n / 256));
-  }
-  K = std::max<int64_t>(1, std::min<int64_t>(K, n));
+  int64_t K = initial_parts(c, n, o.part_nodes);
   const size_t plan_mark = g->arena.used;  // each plan attempt reuses the same workspace
   for (int attempt = 0;; ++attempt) {
     if (g->arena.base) {
@@ -453,7 +455,7 @@ int ditr_workspace_bytes(ditr_ctx* c, int64_t n, int64_t nnz, int nrhs, const di
   ditr_opts_default(&o);
   if (opts) o = *opts;
   if (nrhs == 0) {
-    *bytes = graph_workspace_bound(c, n, nnz, o.part_type, n);
+    *bytes = graph_workspace_bound(c, n, nnz, o.part_type, initial_parts(c, n, o.part_nodes), n);
     return DITR_OK;
   }
   if (nrhs < 4 || nrhs > 256 || nrhs % 4)

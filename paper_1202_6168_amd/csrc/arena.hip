@@ -40,15 +40,16 @@ void g_free(ditr_graph* g, void* p) {
 }
 
 // Upper bound of the device bytes ditr_graph_upload_csc takes for a PageRank
-// graph of n nodes and nnz links whose plans have at most K_max partitions
-// (the plan loop may raise K up to n). Per link: the transpose (4 B), local
+// graph of n nodes and nnz links whose plans have between K_min and K_max
+// partitions (the plan loop starts at K_min and may raise K up to n). Per link: the transpose (4 B), local
 // targets (2 B), external in-links (at most 6 B, light or heavy), heavy items
 // (at most nnz / 5 of them, 20 B each with their words) and their work units
 // (at most 0.45 nnz / 64 + 9 units of 2304 B). Per node: the transpose
 // pointer, heavy-row list, exact-residual work array, pull-sweep shares, plan
 // ids, local ids, weights, counts and their scans. Per partition: pointers,
 // thresholds, locks, sums.
-size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part_type, int64_t K_max) {
+size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part_type, int64_t K_min,
+                             int64_t K_max) {
   const size_t N = (size_t)n, L = (size_t)std::max<int64_t>(nnz, 1), K = (size_t)std::max<int64_t>(K_max, 1);
   const size_t tiles = N / 4096 + 2;
   const size_t nh = std::min<size_t>(N, L / (kHeavyRow + 1) + 1);
@@ -68,7 +69,7 @@ size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part
   // one partition plan (each retry reuses the same space)
   b += al(4 * (K + 1)) + al(8 * K) + al(4 * K) + al(8 * (K + 1));
   if (part_type == DITR_PART_PMASS) b += pmass_temp_bytes(n, nnz);
-  if (part_type == DITR_PART_MINCUT) b += mincut_temp_bytes(n, (int64_t)K);
+  if (part_type == DITR_PART_MINCUT) b += mincut_temp_bytes(n, K_min, (int64_t)K);
   // the partitioned-sweep tables and the temporaries of their build (left in
   // place in a workspace): ids, local CSC, external links, heavy rows, items
   // and their work units, the two sorts, six scans

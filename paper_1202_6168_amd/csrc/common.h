@@ -156,7 +156,9 @@ hipError_t g_alloc(ditr_graph* g, void** p, size_t bytes);
 void g_free(ditr_graph* g, void* p);
 bool workspace_overflow(bool reset);  // whether a workspace allocation failed on this thread
 // upper bound of the workspace a graph upload needs (ditr_workspace_bytes)
-size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part_type, int64_t K_max);
+size_t graph_workspace_bound(const ditr_ctx* c, int64_t n, int64_t nnz, int part_type, int64_t K_min,
+                             int64_t K_max);
+int64_t initial_parts(const ditr_ctx* c, int64_t n, int32_t part_nodes);
 size_t batch_workspace_bytes(const ditr_ctx* c, int64_t n, int64_t n_heavy, int R);
 
 // ---- error reporting (api.hip) ------------------------------------------
@@ -279,7 +281,7 @@ size_t pmass_temp_bytes(int64_t n, int64_t nnz);
 int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* col_ptr, const int32_t* row_idx,
                             const int32_t* in_ptr, int64_t K, int64_t* out64, int32_t* out32,
                             ditr_graph* g = nullptr);
-size_t mincut_temp_bytes(int64_t n, int64_t K);
+size_t mincut_temp_bytes(int64_t n, int64_t K_min, int64_t K_max);
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f);
 int launch_check_finite(ditr_ctx* c, int64_t n, const double* x);

@@ -518,12 +518,16 @@ int launch_partition_mincut(ditr_ctx* c, int64_t n, int64_t nnz, const int32_t* 
 
 // device bytes launch_partition_mincut takes for its temporaries (an upper
 // bound, with the scans' own scratch)
-size_t mincut_temp_bytes(int64_t n, int64_t K) {
+// (an upper bound over every partition count in [K_min, K_max], with the
+// scans' own scratch)
+size_t mincut_temp_bytes(int64_t n, int64_t K_min, int64_t K_max) {
   auto al = [](size_t x) { return (std::max<size_t>(x, 16) + 255) & ~(size_t)255; };
-  const McSizes ss = mc_scan_sizes(n, K);
-  const size_t N = (size_t)n, KK = (size_t)std::max<int64_t>(K, 1);
-  const size_t W = ((N + KK - 1) / KK) / 2;
+  const McSizes ss = mc_scan_sizes(n, K_max);
+  const size_t N = (size_t)n, KK = (size_t)std::max<int64_t>(K_max, 1);
+  // the widest windows come with the fewest partitions
+  const size_t W = ((N + (size_t)std::max<int64_t>(K_min, 1) - 1) / (size_t)std::max<int64_t>(K_min, 1)) / 2;
+  // back-pointers: (K + 1)(2 w + 1) <= (K + 1)(ceil(N/K) + 1) <= 3 (N + 1) for any K in [1, N]
   return 3 * al(8 * (N + 1)) + 2 * al(4 * (N + 1)) + 3 * al(8 * (KK + 1)) + 2 * al(8 * (KK + 2)) + al(16) +
-         3 * al(8 * (2 * W + 2)) + al(4 * (2 * W + 2)) + al(4 * (KK + 1) * (2 * W + 1)) + al(4) + al(ss.scan_n) +
+         3 * al(8 * (2 * W + 2)) + al(4 * (2 * W + 2)) + al(12 * (N + 1)) + al(4) + al(ss.scan_n) +
          al(ss.scan_k) + al(ss.scan_x) + al(ss.scan_t) + 4096;
 }

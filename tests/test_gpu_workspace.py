@@ -36,9 +36,12 @@ def _problem(n, seed, block=1000):
     return cp, ri, torch.from_numpy(cp).to(dev), torch.from_numpy(ri).to(dev)
 
 
-@pytest.mark.parametrize("part_type", [ditr.PART_CB_INOUT, ditr.PART_PMASS, ditr.PART_MINCUT])
-def test_upload_into_workspace_and_solve(ctx, part_type):
-    cp, ri, cpt, rit = _problem(60_000, 41)
+@pytest.mark.parametrize("part_type,n", [(ditr.PART_CB_INOUT, 60_000), (ditr.PART_PMASS, 60_000),
+                                         (ditr.PART_MINCUT, 60_000), (ditr.PART_MINCUT, 1_000_000)])
+def test_upload_into_workspace_and_solve(ctx, part_type, n):
+    # at 1e6 nodes the cut-minimizing plan's windows (~3900 positions) are the
+    # widest its workspace bound has to cover
+    cp, ri, cpt, rit = _problem(n, 41)
     n, nnz = cp.size - 1, ri.size
     opts = ditr.opts_default(part_type=part_type)
     nbytes = ditr.workspace_bytes(ctx, n, nnz, 0, opts)
