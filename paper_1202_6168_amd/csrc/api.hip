@@ -549,8 +549,22 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
 
   int rc = launch_reset_ctrl(c);
   if (rc) return finish(rc);
+  // A cold partitioned solve whose partitions are all resident queues its
+  // usual two stages without host readbacks in between (init, stage, exact
+  // refresh, stage, exact refresh): each stage's parameters come from the
+  // device's own sums, and a stage made unnecessary returns at once. Further
+  // stages, if any, go through the loop below.
+  bool pipelined = false;
+  if (!warm && (o.mode == DITR_MODE_AUTO || o.mode == DITR_MODE_PARTITION) && !g->val && !g->colabs &&
+      !(o.flags & DITR_FLAG_NO_RESIDENT) && o.max_rounds >= 2 && g->part_ptr && g->pp.ready) {
+    rc = part_resident_fits(c, g, &pipelined, (o.flags & DITR_FLAG_PRIORITY) != 0);
+    if (rc) return finish(rc);
+  }
   double b1 = 0, r = 0, fmax = 0;
-  if (!warm) {
+  if (!warm && pipelined) {
+    rc = launch_init(c, n, d_b, d_h, d_f);  // read back after the stages
+    if (rc) return finish(rc);
+  } else if (!warm) {
     // F = B, H = 0; ||B||_1, ||F_0||_1 and max |F_0| in one pass
     rc = launch_init(c, n, d_b, d_h, d_f);
     if (!rc) rc = read_ctrl(c);
@@ -587,7 +601,7 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     st.refreshes += 1;
   }
   st.b_l1 = b1;
-  const double target = rel_tol * b1;
+  double target = rel_tol * b1;
   // a warm start's FP32 fluid drifts like a cold one's: the same first stage applies
   bool refreshed = false;
 
@@ -711,6 +725,44 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   double t_carry = 0;
   bool resident_ran = false;
   bool must_refresh = warm == 2;  // a given F_0 is trusted for one stage only
+  if (pipelined) {
+    for (int s = 0; s < 2; ++s) {
+      rc = launch_part_stage(c, g, sb, s == 0, rel_tol, refresh_at, o.alpha);
+      if (!rc && timed && hipEventRecord(ev[2 * s], c->stream) != hipSuccess)
+        rc = set_error(DITR_EHIP, "hipEventRecord failed");
+      if (!rc)
+        rc = launch_part_resident(c, g, sb, d_f, d_h, o.alpha, o.sweeps_per_claim > 0 ? o.sweeps_per_claim : 3,
+                                  o.max_sweeps > 0 ? (int)std::min<int64_t>(o.max_sweeps, 1 << 30) : 4096, prio);
+      if (!rc && timed && hipEventRecord(ev[2 * s + 1], c->stream) != hipSuccess)
+        rc = set_error(DITR_EHIP, "hipEventRecord failed");
+      if (!rc) rc = launch_refresh_bufs(c, g, d_b, d_h, d_f, sb.wh, sb.chunk_sum);
+      if (rc) return finish(rc);
+    }
+    rc = read_ctrl(c);
+    if (rc) return finish(rc);
+    const Ctrl& h = *c->ctrl_host;
+    if (h.err == 2) return finish(set_error(DITR_EHIP, "a wait of the resident sweep timed out"));
+    if (h.err) return finish(set_error(DITR_ENONFINITE, "B holds NaN or Inf"));
+    b1 = h.b1;
+    st.b_l1 = b1;
+    target = rel_tol * b1;
+    st.rounds = h.stages;
+    st.launches += h.stages;
+    st.refreshes += 2;
+    resident_ran = h.stages > 0;
+    refreshed = true;
+    t_carry = h.T;
+    r = h.sum_abs;
+    fmax = h.max_abs;
+    if (timed)
+      for (int s = 0; s < h.stages; ++s) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]));
+        st.kernel_seconds += 1e-3 * ms;
+        st.timed_launches += 1;
+      }
+    if (!std::isfinite(r)) return finish(set_error(DITR_ENONFINITE, "residual became non-finite"));
+  }
   while (r > target || must_refresh) {
     must_refresh = false;
     if (st.rounds >= o.max_rounds) {

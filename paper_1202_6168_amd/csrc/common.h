@@ -23,7 +23,8 @@ struct Ctrl {
   int done;
   int ticket;
   int err;                 // graph validation / non-finite input flag
-  int pad;
+  int stages;              // resident stages that ran (pipelined solve)
+  double b1;               // ||B||_1 of the solve (pipelined solve)
 };
 
 struct ditr_ctx {
@@ -304,6 +305,8 @@ int part_configure(ditr_ctx* c);
 size_t part_lds_bytes(int nodes, int local_edges, bool prio = false);
 size_t plan_sort_temp_bytes(int64_t n, int64_t ni);
 int graph_set_plan(ditr_ctx* c, ditr_graph* g, const int64_t* h_ptr, int64_t K);
+int launch_part_stage(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, int first, double rel_tol,
+                      double refresh_at, double alpha);
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,
                         double target, double T0);
 int launch_part_sweeps(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, float* f, double* h,

@@ -953,6 +953,10 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
   __shared__ double red[4][NW];
   __shared__ int s_ok;
   extern __shared__ __align__(16) unsigned char smem[];
+  // a queued stage the previous one made unnecessary (its start meets the
+  // target) returns at once; every workgroup reads the flag before any of them
+  // can finish a level, so the end-of-stage write below cannot race with it
+  if (a.ctrl->done) return;
   const int p = blockIdx.x;
   const PartView v = part_view(a, smem, p);
   int* arrive = a.counters + 6;
@@ -1090,6 +1094,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_resident(PartArgs a, int spin_li
     a.ctrl->sweeps += (unsigned long long)levels;
     a.ctrl->T = T;
     a.ctrl->done = done;
+    a.ctrl->stages += 1;
   }
 }
 
@@ -1417,6 +1422,54 @@ __global__ void k_part_prepare(Ctrl* ctrl, double r0, double target, double T0, 
   }
   if (i0 < kCounters) counters[i0] = 0;
   for (int64_t i = i0; i < n2; i += stride) S[i] = 0.f;
+}
+
+// Parameters of the next stage of a solve queued without host readbacks, from
+// the device's own sums (one thread): the first stage reads the init pass
+// (||B||_1, ||F_0||_1, max |F_0|), a later one the exact refresh before it
+// (||F||_1, max |F|) and the threshold the previous stage ended at; the same
+// rules as the host's stage loop. A stage whose start already meets the target,
+// or that follows a non-finite input or a timed-out wait, is marked done, and
+// its launch returns at once.
+__global__ void k_part_stage(Ctrl* ctrl, int first, int64_t n, double rel_tol, double refresh_at, double alpha) {
+  if (first) ctrl->b1 = ctrl->sum_abs;
+  const double b1 = ctrl->b1;
+  const double r = first ? ctrl->sum_abs_f32 : ctrl->sum_abs;
+  const double mx = ctrl->max_abs;
+  const double target = rel_tol * b1;
+  double stage, T0;
+  if (first) {
+    stage = r > refresh_at * b1 ? fmax(target, refresh_at * b1) : 0.5 * target;
+    T0 = fmin(mx / alpha, r / (double)(n > 1 ? n : 1));
+  } else {
+    stage = 0.5 * target;
+    T0 = fmin(ctrl->T, mx / alpha);
+  }
+  T0 = fmax(T0, r * kPartTFloor);
+  ctrl->destroyed = 0;
+  ctrl->r0 = r;
+  ctrl->target = stage;
+  ctrl->T = T0;
+  ctrl->ticket = 0;
+  ctrl->passed = 0;
+  ctrl->done = (ctrl->err != 0 || !(r > target)) ? 1 : 0;
+}
+
+// the zeroing part of k_part_prepare (counters, shares)
+__global__ void k_part_clear(int* counters, float* S, int64_t n2) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  if (i0 < kCounters) counters[i0] = 0;
+  for (int64_t i = i0; i < n2; i += stride) S[i] = 0.f;
+}
+
+int launch_part_stage(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, int first, double rel_tol,
+                      double refresh_at, double alpha) {
+  k_part_stage<<<1, 1, 0, c->stream>>>(c->ctrl, first, g->n, rel_tol, refresh_at, alpha);
+  HIP_TRY(hipGetLastError());
+  k_part_clear<<<std::min<int64_t>(4096, std::max<int64_t>(1, (2 * g->n + 255) / 256)), 256, 0, c->stream>>>(
+      sb.counters, sb.S, 2 * g->n);
+  HIP_TRY(hipGetLastError());
+  return DITR_OK;
 }
 
 int launch_part_prepare(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, double r0,

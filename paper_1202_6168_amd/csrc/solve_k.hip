@@ -270,6 +270,8 @@ __global__ void k_reset_ctrl(Ctrl* c) {
   c->done = 0;
   c->ticket = 0;
   c->err = 0;
+  c->stages = 0;
+  c->b1 = 0;
 }
 
 // start of a diffusion launch: r0 = ||F||_1 (exact), target, T0
