@@ -1429,9 +1429,10 @@ __global__ void k_part_prepare(Ctrl* ctrl, double r0, double target, double T0, 
 // (||B||_1, ||F_0||_1, max |F_0|), a later one the exact refresh before it
 // (||F||_1, max |F|) and the threshold the previous stage ended at; the same
 // rules as the host's stage loop. A stage whose start already meets the target,
-// or that follows a non-finite input or a timed-out wait, is marked done, and
-// its launch returns at once.
-__global__ void k_part_stage(Ctrl* ctrl, int first, int64_t n, double rel_tol, double refresh_at, double alpha) {
+// or that follows a non-finite input, a timed-out wait or an abort, is marked
+// done, and its launch returns at once.
+__global__ void k_part_stage(Ctrl* ctrl, const int* abort_flag, int first, int64_t n, double rel_tol,
+                             double refresh_at, double alpha) {
   if (first) ctrl->b1 = ctrl->sum_abs;
   const double b1 = ctrl->b1;
   const double r = first ? ctrl->sum_abs_f32 : ctrl->sum_abs;
@@ -1452,7 +1453,9 @@ __global__ void k_part_stage(Ctrl* ctrl, int first, int64_t n, double rel_tol, d
   ctrl->T = T0;
   ctrl->ticket = 0;
   ctrl->passed = 0;
-  ctrl->done = (ctrl->err != 0 || !(r > target)) ? 1 : 0;
+  // an abort raised during the previous stage skips this one too
+  const int aborted = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+  ctrl->done = (ctrl->err != 0 || aborted || !(r > target)) ? 1 : 0;
 }
 
 // the zeroing part of k_part_prepare (counters, shares)
@@ -1464,7 +1467,7 @@ __global__ void k_part_clear(int* counters, float* S, int64_t n2) {
 
 int launch_part_stage(ditr_ctx* c, const ditr_graph* g, const SolveBufs& sb, int first, double rel_tol,
                       double refresh_at, double alpha) {
-  k_part_stage<<<1, 1, 0, c->stream>>>(c->ctrl, first, g->n, rel_tol, refresh_at, alpha);
+  k_part_stage<<<1, 1, 0, c->stream>>>(c->ctrl, c->abort_dev, first, g->n, rel_tol, refresh_at, alpha);
   HIP_TRY(hipGetLastError());
   k_part_clear<<<std::min<int64_t>(4096, std::max<int64_t>(1, (2 * g->n + 255) / 256)), 256, 0, c->stream>>>(
       sb.counters, sb.S, 2 * g->n);
