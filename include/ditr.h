@@ -256,7 +256,7 @@ int ditr_graph_partitions(const ditr_graph* g, int64_t* K_out, int64_t* h_ptr, i
  *     out-degrees multiply to at most 2, spanning fewer than 2 ceil(n/K) ids;
  *   - the plan minimizes sum_k cross(b_k); among equal sums b_{K-1} is the
  *     smallest possible, then b_{K-2}, and so on.
- * Takes device temporaries of about 32 bytes per node; EINVAL if no plan is
+ * Takes device temporaries of about 40 bytes per node; EINVAL if no plan is
  * found (cannot happen for valid input: the targets are feasible).
  * Synchronizes for CB_INOUT and MINCUT (temporary in-link prefix). */
 int ditr_partition(ditr_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_col_ptr,
