@@ -377,7 +377,8 @@ typedef struct {
 
 /* Pick the options of the plain solve that reach rel_tol ||B||_1 fastest on
  * this problem: partition type and nodes per partition (Section 2.3), the
- * threshold divisor alpha in [1.2, 2] (Section 2.4), local sweeps per launch
+ * threshold divisor alpha in [1.2, 3] (Section 2.4 finds [1.2, 2]
+ * uninfluential; on the GPU a larger one can pay), local sweeps per level
  * and the first exact-refresh point, by coordinate descent over wall time to
  * tolerance (effort 0: partition size and alpha; 1: also local sweeps and the
  * refresh point; 2: a second pass). The returned options are never slower than
