@@ -141,14 +141,18 @@ __global__ void __launch_bounds__(kRedBlock) k_check_finite(int64_t n, const dou
 }
 
 // reduce partials[0..nb) (sum of slot 0, max of slot 1, sum of slot 2) into ctrl
-__global__ void __launch_bounds__(kRedBlock) k_finalize(const double* partials, int nb, Ctrl* ctrl) {
+// (one workgroup of kFinBlock threads, eight partials of each in flight at once:
+// a lone workgroup waits out every load it cannot overlap)
+constexpr int kFinBlock = 1024;
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const double* partials, int nb, Ctrl* ctrl) {
   double s = 0, s2 = 0, m = 0;
-  for (int i = threadIdx.x; i < nb; i += kRedBlock) {
+#pragma unroll 8
+  for (int i = threadIdx.x; i < nb; i += kFinBlock) {
     s += partials[kPartialStride * i + 0];
     m = fmax(m, partials[kPartialStride * i + 1]);
     s2 += partials[kPartialStride * i + 2];
   }
-  block_reduce3<kRedBlock>(s, s2, m);
+  block_reduce3<kFinBlock>(s, s2, m);
   if (threadIdx.x == 0) {
     ctrl->sum_abs = s;
     ctrl->max_abs = m;
@@ -636,7 +640,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(PArgs a) {
 // launchers
 
 static int finalize_partials(ditr_ctx* c, int nb) {
-  k_finalize<<<1, kRedBlock, 0, c->stream>>>(c->partials, nb, c->ctrl);
+  k_finalize<<<1, kFinBlock, 0, c->stream>>>(c->partials, nb, c->ctrl);
   HIP_TRY(hipGetLastError());
   return DITR_OK;
 }
