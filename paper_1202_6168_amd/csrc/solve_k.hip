@@ -235,20 +235,18 @@ __global__ void __launch_bounds__(kRedBlock) k_refresh_main(
   }
 }
 
-// heavy rows: each thread adds the chunk sums of one row in chunk order
+// heavy rows: chunks are grouped by heavy row, in row order; the thread that
+// holds a row's first chunk adds the row's chunk sums in chunk order
 __global__ void __launch_bounds__(kRedBlock) k_refresh_heavy_fin(
-    int32_t n_heavy, const int32_t* __restrict__ rows, const int32_t* __restrict__ chunk_h,
-    int32_t n_chunks, const double* __restrict__ chunk_sum, const double* __restrict__ b,
-    const double* __restrict__ h, float* __restrict__ f, double* partials) {
+    const int32_t* __restrict__ rows, const int32_t* __restrict__ chunk_h, int32_t n_chunks,
+    const double* __restrict__ chunk_sum, const double* __restrict__ b, const double* __restrict__ h,
+    float* __restrict__ f, double* partials) {
   double s = 0, unused = 0, m = 0;
-  for (int32_t r = blockIdx.x * kRedBlock + threadIdx.x; r < n_heavy; r += gridDim.x * kRedBlock) {
-    int32_t lo = 0, hi = n_chunks;  // first chunk of row r
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (chunk_h[mid] < r) lo = mid + 1; else hi = mid;
-    }
+  for (int32_t c = blockIdx.x * kRedBlock + threadIdx.x; c < n_chunks; c += gridDim.x * kRedBlock) {
+    const int32_t r = chunk_h[c];
+    if (c > 0 && chunk_h[c - 1] == r) continue;
     double acc = 0;
-    for (int32_t c = lo; c < n_chunks && chunk_h[c] == r; ++c) acc += chunk_sum[c];
+    for (int32_t k = c; k < n_chunks && chunk_h[k] == r; ++k) acc += chunk_sum[k];
     const int32_t j = rows[r];
     const double v = b[j] - h[j] + acc;
     f[j] = (float)v;
@@ -706,7 +704,7 @@ int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const
   // light rows and the heavy chunks in one launch, then the heavy rows from
   // their chunk sums (every sum in a fixed order)
   const int cap = (int)c->partials_cap;
-  const int nf = g->n_heavy > 0 ? std::min(64, (g->n_heavy + kRedBlock - 1) / kRedBlock) : 0;
+  const int nf = g->n_heavy > 0 ? std::min(64, (g->n_chunks + kRedBlock - 1) / kRedBlock) : 0;
   const int nl = grid_for(n, kRedBlock / 8, cap - nf);
   const int nc = g->n_heavy > 0 ? g->n_chunks : 0;
   if (general)
@@ -719,8 +717,8 @@ int launch_refresh_bufs(ditr_ctx* c, const ditr_graph* g, const double* b, const
                                                                 g->chunk_end, chunk_sum);
   HIP_TRY(hipGetLastError());
   if (nf > 0) {
-    k_refresh_heavy_fin<<<nf, kRedBlock, 0, c->stream>>>(g->n_heavy, g->heavy_rows, g->chunk_h,
-                                                         g->n_chunks, chunk_sum, b, h, f,
+    k_refresh_heavy_fin<<<nf, kRedBlock, 0, c->stream>>>(g->heavy_rows, g->chunk_h, g->n_chunks, chunk_sum,
+                                                         b, h, f,
                                                          c->partials + kPartialStride * nl);
     HIP_TRY(hipGetLastError());
   }
