@@ -66,15 +66,24 @@ __global__ void __launch_bounds__(kRedBlock) k_init(int64_t n, const double* __r
   double s = 0, s32 = 0, m = 0;
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * kRedBlock;
-  for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < n; i += stride) {
-    double v = b[i];
-    bad |= !isfinite(v);
-    float v32 = (float)v;
-    f[i] = v32;
-    h[i] = 0.0;
-    s += fabs(v);
-    s32 += fabs((double)v32);
-    m = fmax(m, fabs(v));
+  constexpr int U = 4;  // four loads of B in flight per thread
+  for (int64_t i0 = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i0 < n; i0 += U * stride) {
+    double bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) bv[u] = i0 + u * stride < n ? b[i0 + u * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i >= n) continue;
+      const double v = bv[u];
+      bad |= !isfinite(v);
+      const float v32 = (float)v;
+      f[i] = v32;
+      h[i] = 0.0;
+      s += fabs(v);
+      s32 += fabs((double)v32);
+      m = fmax(m, fabs(v));
+    }
   }
   if (bad) atomicOr(err, 1);
   block_reduce3<kRedBlock>(s, s32, m);
@@ -663,7 +672,7 @@ int launch_fill_double(ditr_ctx* c, double* p, int64_t n, double v) {
 }
 
 int launch_init(ditr_ctx* c, int64_t n, const double* b, double* h, float* f) {
-  const int nb = grid_for(n, kRedBlock, (int)c->partials_cap);
+  const int nb = grid_for(n, 4 * kRedBlock, (int)c->partials_cap);
   k_init<<<nb, kRedBlock, 0, c->stream>>>(n, b, h, f, c->partials, &c->ctrl->err);
   HIP_TRY(hipGetLastError());
   return finalize_partials(c, nb);
