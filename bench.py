@@ -343,15 +343,27 @@ def warm_bench(ctx, dev, epochs=40):
     }
 
 
-def tuned_bench(ctx, cpt, rit, bt, ht, ft, args, nnz):
+def tuned_bench(ctx, cpt, rit, bt, ht, ft, args, nnz, proxy=None):
     """The same solve with the options the library's tuner picks for this
     problem (partition type and size, alpha, local sweeps, refresh point);
-    the tuning runs before, outside the timing."""
+    the tuning runs before, outside the timing. proxy: a GraphSpec of the
+    same generator to tune on instead (the 5e7-node graph is tuned on a
+    5e6-node one, so that each candidate solve takes milliseconds)."""
     import torch
+    import ditgen
     from paper_1202_6168_amd import ditr
 
     t0 = time.perf_counter()
-    o, info = ditr.tune(ctx, cpt, rit, bt, ht, ft, rel_tol=args.tol, effort=1)
+    if proxy is None:
+        o, info = ditr.tune(ctx, cpt, rit, bt, ht, ft, rel_tol=args.tol, effort=1)
+    else:
+        dev = cpt.device
+        pcp, pri = ditgen.generate(proxy)
+        pt = [torch.from_numpy(a).to(dev) for a in (pcp, pri, ditgen.uniform_b(proxy.n))]
+        ph = torch.empty(proxy.n, dtype=torch.float64, device=dev)
+        pf = torch.empty(proxy.n, dtype=torch.float32, device=dev)
+        o, info = ditr.tune(ctx, pt[0], pt[1], pt[2], ph, pf, rel_tol=args.tol, effort=0)
+        del pt, ph, pf
     tune_s = time.perf_counter() - t0
     g = ditr.Graph(ctx, cpt, rit, opts=ditr.opts_default(part_type=o.part_type, part_nodes=o.part_nodes))
     for _ in range(args.warmup):
@@ -503,8 +515,11 @@ def main():
     }
     if resident and args.mode in (0, 3) and not args.weighted:
         out["trace"] = trace_summary(ctx, g, bt, ht, ft, args.tol, opts, K, dev)
-    if not args.no_tuned and not args.large and args.mode == 0 and not args.weighted and not args.priority:
-        out["tuned"] = tuned_bench(ctx, cpt, rit, bt, ht, ft, args, ri.size)
+    if not args.no_tuned and args.mode == 0 and not args.weighted and not args.priority:
+        proxy = ditgen.GraphSpec(n=5_000_000, block=1000, seed=31) if args.large else None
+        out["tuned"] = tuned_bench(ctx, cpt, rit, bt, ht, ft, args, ri.size, proxy=proxy)
+        if proxy is not None:
+            out["tuned"]["tuned_on"] = "same-generator proxy, 5e6 nodes, seed 31"
     if not args.no_batched:
         out["batched"] = batched_bench(ctx, g, spec.n, dev)
     g.close()
