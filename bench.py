@@ -394,7 +394,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the solver has no multi-GPU path in this build "
+        print("bench.py runs on one GPU: the solver has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

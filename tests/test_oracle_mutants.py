@@ -95,7 +95,7 @@ def build_variant(tmp_path, name):
 
 
 def pin_suite(lib):
-    """Return the names of the pins that fail for this build."""
+    """Return the names of the pins that fail for this oracle library."""
     fails = []
     try:
         for c in json.load(open(GOLDEN))["cases"]:
