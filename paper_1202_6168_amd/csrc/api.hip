@@ -553,16 +553,20 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   // usual two stages without host readbacks in between (init, stage, exact
   // refresh, stage, exact refresh): each stage's parameters come from the
   // device's own sums, and a stage made unnecessary returns at once. Further
-  // stages, if any, go through the loop below.
+  // stages, if any, go through the loop below. A start with the caller's F_0
+  // (warm = 2) is queued the same way after its one pass over B, H_0 and F_0;
+  // both stages end with an exact refresh, so the result is certified on an
+  // exact residual whatever the given F_0 was.
   bool pipelined = false;
-  if (!warm && (o.mode == DITR_MODE_AUTO || o.mode == DITR_MODE_PARTITION) && !g->val && !g->colabs &&
+  if ((!warm || warm == 2) && (o.mode == DITR_MODE_AUTO || o.mode == DITR_MODE_PARTITION) && !g->val && !g->colabs &&
       !(o.flags & DITR_FLAG_NO_RESIDENT) && o.max_rounds >= 2 && g->part_ptr && g->pp.ready) {
     rc = part_resident_fits(c, g, &pipelined, (o.flags & DITR_FLAG_PRIORITY) != 0);
     if (rc) return finish(rc);
   }
   double b1 = 0, r = 0, fmax = 0;
-  if (!warm && pipelined) {
-    rc = launch_init(c, n, d_b, d_h, d_f);  // read back after the stages
+  if (pipelined) {
+    // read back after the stages
+    rc = warm == 2 ? launch_given_start(c, n, d_b, d_h, d_f) : launch_init(c, n, d_b, d_h, d_f);
     if (rc) return finish(rc);
   } else if (!warm) {
     // F = B, H = 0; ||B||_1, ||F_0||_1 and max |F_0| in one pass
@@ -724,7 +728,7 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
   int status = DITR_OK;
   double t_carry = 0;
   bool resident_ran = false;
-  bool must_refresh = warm == 2;  // a given F_0 is trusted for one stage only
+  bool must_refresh = warm == 2 && !pipelined;  // a given F_0 is trusted for one stage only
   if (pipelined) {
     for (int s = 0; s < 2; ++s) {
       rc = launch_part_stage(c, g, sb, s == 0, rel_tol, refresh_at, o.alpha);
@@ -742,7 +746,8 @@ int solve_impl(ditr_ctx* c, const ditr_graph* g, const double* d_b, double* d_h,
     if (rc) return finish(rc);
     const Ctrl& h = *c->ctrl_host;
     if (h.err == 2) return finish(set_error(DITR_EHIP, "a wait of the resident sweep timed out"));
-    if (h.err) return finish(set_error(DITR_ENONFINITE, "B holds NaN or Inf"));
+    if (h.err)
+      return finish(set_error(DITR_ENONFINITE, warm == 2 ? "B, H_0 or F_0 holds NaN or Inf" : "B holds NaN or Inf"));
     b1 = h.b1;
     st.b_l1 = b1;
     target = rel_tol * b1;
